@@ -1,0 +1,418 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the diffuse-radiation ray-tracing
+ * sweep of Tanaka, Yoshikawa, Okamoto & Hasegawa, "A new ray-tracing scheme
+ * for 3D diffuse radiation transfer on highly parallel architectures"
+ * (PASJ; arXiv:1410.0763), Sect. 2.2 (eqs rt, path_averaged_intensity,
+ * averaged_intensity, mean_intensity), Sect. 2.3 (HEALPix directions) and
+ * Sect. 3.1 (ray grouping).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or helper with the HIP implementation; the product
+ * path never calls it.
+ *
+ * Everything is double precision and deliberately simple:
+ *   - directions are HEALPix RING pixel centres written from the formulas of
+ *     Gorski et al. (2005), the package the paper uses (Sect. 2.3);
+ *   - a ray's cell segments are found by collecting every integer-plane
+ *     crossing along the ray, sorting them, and taking the cell that contains
+ *     the midpoint of each consecutive pair (no incremental stepping);
+ *   - the per-(direction, cell) averages are normalised literally with the
+ *     optical-depth weights of eq averaged_intensity, direction by direction;
+ *   - OpenMP runs the rays of one ray group (Sect. 3.1) in parallel: rays of a
+ *     group never share a cell, so the per-direction scratch needs no locks.
+ *
+ * Readings of points the paper leaves open (each one is listed in the design doc):
+ *   Q1 ray lattice: for direction n with dominant axis a (sign sig) and the
+ *      other two axes b < c, ray (j,k) is the line
+ *         x_a = s (sig>0) or N_a - s (sig<0),  x_b = j + 1/2 + t_b s,
+ *         x_c = k + 1/2 + t_c s,   t_b = n_b/|n_a|, t_c = n_c/|n_a|,
+ *      for depth s in [0, N_a], in cell units; every (j,k) whose chord through
+ *      the box is positive is cast.  Ray spacing equals the cell size.
+ *   Q2 dominant-axis ties: the lowest axis index among the components within
+ *      1e-12 of the largest |n_i|.  Components below 1e-12 are set to zero.
+ *   Q3 kappa = 0: the optical-depth weights are 0/0; the limit (path-length
+ *      weights, phi(0) = 1) is used.
+ *   Q4 the paper's J = J_in + S (eq mean_intensity) is returned, and in
+ *      addition J_exact = J_in + S * <1 - phi>, the exact path average of the
+ *      formal solution (eq rad_tr2) with constant S in a cell.
+ *   Q5 Gamma = sum_b g_b (J_in_b + S_b) with caller weights g_b: the affine
+ *      form of eq gamma_diff with the frequency integral folded into g_b.
+ *   Q6 the intensity entering the box is a uniform I_bc.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_TIE 1e-12
+#define ORACLE_SLIVER 1e-12
+
+/* ------------------------------------------------------------------------ */
+/* Directions: HEALPix RING pixel centres (Sect. 2.3; Gorski et al. 2005).   */
+/* Rings i = 1 .. 4N-1 from north to south; pixels j = 1 .. ring size.      */
+/* ------------------------------------------------------------------------ */
+int oracle_ndirs(int nside) { return 12 * nside * nside; }
+
+int oracle_directions(int nside, double *n_out)
+{
+    if (nside < 1) return -1;
+    const double N = (double)nside;
+    int idx = 0;
+    for (int i = 1; i <= 4 * nside - 1; ++i) {
+        double z;
+        int npix;
+        double dphi, phi0;
+        if (i < nside) {                      /* north polar cap */
+            z = 1.0 - (double)i * i / (3.0 * N * N);
+            npix = 4 * i;
+            dphi = M_PI / (2.0 * i);
+            phi0 = 0.5 * dphi;                /* phi = dphi (j - 1/2) */
+        } else if (i <= 3 * nside) {          /* equatorial belt */
+            z = 4.0 / 3.0 - 2.0 * i / (3.0 * N);
+            npix = 4 * nside;
+            dphi = M_PI / (2.0 * N);
+            /* phi = dphi (j - s/2) with s = (i - N + 1) mod 2; rings with s = 0
+               are numbered from phi = 0 as in the HEALPix library */
+            int s = (i - nside + 1) % 2;
+            phi0 = s ? 0.5 * dphi : 0.0;
+        } else {                              /* south polar cap: mirror */
+            int ip = 4 * nside - i;
+            z = -(1.0 - (double)ip * ip / (3.0 * N * N));
+            npix = 4 * ip;
+            dphi = M_PI / (2.0 * ip);
+            phi0 = 0.5 * dphi;
+        }
+        double st = sqrt((1.0 - z) * (1.0 + z));
+        for (int j = 0; j < npix; ++j) {
+            double phi = phi0 + dphi * j;
+            double v[3] = {st * cos(phi), st * sin(phi), z};
+            for (int q = 0; q < 3; ++q)
+                if (fabs(v[q]) < ORACLE_TIE) v[q] = 0.0;
+            n_out[3 * idx + 0] = v[0];
+            n_out[3 * idx + 1] = v[1];
+            n_out[3 * idx + 2] = v[2];
+            ++idx;
+        }
+    }
+    return idx;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parallel-ray lattice of one direction (Sect. 2.2, Fig. parallel_ray;      */
+/* reading Q1/Q2 above).                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int a, b, c;      /* dominant axis and the two others (b < c) */
+    int sig;          /* +1: rays travel towards +x_a, -1: towards -x_a */
+    double w;         /* |n_a|: unit depth is a path length of 1/w cells */
+    double tb, tc;    /* transverse slopes n_b/|n_a|, n_c/|n_a| */
+} odir_t;
+
+static void dir_geom(const double *n, odir_t *g)
+{
+    double m = fmax(fabs(n[0]), fmax(fabs(n[1]), fabs(n[2])));
+    int a = 0;
+    while (fabs(n[a]) < m - ORACLE_TIE) ++a;
+    int b = (a == 0) ? 1 : 0;
+    int c = (a == 2) ? 1 : 2;
+    g->a = a; g->b = b; g->c = c;
+    g->sig = n[a] > 0.0 ? 1 : -1;
+    g->w = fabs(n[a]);
+    g->tb = n[b] / g->w;
+    g->tc = n[c] / g->w;
+}
+
+/* Position of ray (j,k) at depth s, in world axes (cell units). */
+static void ray_pos(const odir_t *g, const int *N, int j, int k, double s, double *p)
+{
+    p[g->a] = g->sig > 0 ? s : (double)N[g->a] - s;
+    p[g->b] = j + 0.5 + g->tb * s;
+    p[g->c] = k + 0.5 + g->tc * s;
+}
+
+/* Depth interval where x0 + t s lies in (0, L); returns 0 if empty. */
+static int clip_axis(double x0, double t, double L, double *lo, double *hi)
+{
+    if (t == 0.0) {
+        if (x0 > 0.0 && x0 < L) { *lo = -INFINITY; *hi = INFINITY; return 1; }
+        return 0;
+    }
+    double s0 = (0.0 - x0) / t, s1 = (L - x0) / t;
+    *lo = fmin(s0, s1);
+    *hi = fmax(s0, s1);
+    return 1;
+}
+
+/* Chord of ray (j,k) through the box, as a depth interval. */
+static int ray_clip(const odir_t *g, const int *N, int j, int k, double *sin_, double *sout)
+{
+    double lo = 0.0, hi = (double)N[g->a], l, h;
+    if (!clip_axis(j + 0.5, g->tb, (double)N[g->b], &l, &h)) return 0;
+    lo = fmax(lo, l); hi = fmin(hi, h);
+    if (!clip_axis(k + 0.5, g->tc, (double)N[g->c], &l, &h)) return 0;
+    lo = fmax(lo, l); hi = fmin(hi, h);
+    *sin_ = lo; *sout = hi;
+    return hi > lo;
+}
+
+/* Conservative lattice index ranges [jlo, jhi] x [klo, khi]. */
+static void lattice_range(const odir_t *g, const int *N, int *jlo, int *jhi, int *klo, int *khi)
+{
+    double Na = (double)N[g->a];
+    *jlo = (int)floor(-0.5 - fmax(0.0, g->tb * Na)) - 1;
+    *jhi = (int)ceil((double)N[g->b] - 0.5 - fmin(0.0, g->tb * Na)) + 1;
+    *klo = (int)floor(-0.5 - fmax(0.0, g->tc * Na)) - 1;
+    *khi = (int)ceil((double)N[g->c] - 0.5 - fmin(0.0, g->tc * Na)) + 1;
+}
+
+static int cmp_double(const void *x, const void *y)
+{
+    double a = *(const double *)x, b = *(const double *)y;
+    return (a > b) - (a < b);
+}
+
+/*
+ * Cell segments of ray (j,k): every depth where the line crosses an integer
+ * plane of any axis inside the chord, sorted; each consecutive pair with a
+ * positive gap is one segment, in the cell that holds its midpoint.
+ * Writes cell index (x fastest), path length (cell units times h) and the
+ * segment's entry depth.  Returns the number of segments.
+ */
+static int ray_segments(const odir_t *g, const int *N, double h, int j, int k,
+                        double *buf, int *cell, double *dl, double *s0)
+{
+    double si, so;
+    if (!ray_clip(g, N, j, k, &si, &so)) return 0;
+    int nb = 0;
+    buf[nb++] = si;
+    buf[nb++] = so;
+    double p0[3], p1[3];
+    ray_pos(g, N, j, k, si, p0);
+    ray_pos(g, N, j, k, so, p1);
+    for (int ax = 0; ax < 3; ++ax) {
+        double lo = fmin(p0[ax], p1[ax]), hi = fmax(p0[ax], p1[ax]);
+        for (double m = floor(lo) + 1.0; m < hi; m += 1.0) {
+            double s;
+            if (ax == g->a) s = g->sig > 0 ? m : (double)N[g->a] - m;
+            else if (ax == g->b) s = (m - (j + 0.5)) / g->tb;
+            else s = (m - (k + 0.5)) / g->tc;
+            if (s > si && s < so) buf[nb++] = s;
+        }
+    }
+    qsort(buf, nb, sizeof(double), cmp_double);
+    int ns = 0;
+    for (int q = 0; q + 1 < nb; ++q) {
+        double sa = buf[q], sb = buf[q + 1];
+        /* Crossings that coincide in exact arithmetic (a ray through a cell
+           edge or corner) come out a few ulps apart; such slivers are contacts
+           of zero length and are not segments. */
+        if (!(sb - sa > ORACLE_SLIVER)) continue;
+        double pm[3];
+        ray_pos(g, N, j, k, 0.5 * (sa + sb), pm);
+        int ci[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            int v = (int)floor(pm[ax]);
+            if (v < 0) v = 0;
+            if (v > N[ax] - 1) v = N[ax] - 1;
+            ci[ax] = v;
+        }
+        const int cid = (ci[2] * N[1] + ci[1]) * N[0] + ci[0];
+        if (ns > 0 && cell[ns - 1] == cid) {
+            /* the same cell on both sides of a dropped sliver: one visit */
+            dl[ns - 1] = (sb - s0[ns - 1]) * h / g->w;
+            continue;
+        }
+        cell[ns] = cid;
+        dl[ns] = (sb - sa) * h / g->w;
+        s0[ns] = sa;
+        ++ns;
+    }
+    return ns;
+}
+
+static int max_crossings(const int *N) { return N[0] + N[1] + N[2] + 8; }
+
+/* ------------------------------------------------------------------------ */
+/* Exported geometry helpers (used by the brute-force tests).               */
+/* ------------------------------------------------------------------------ */
+int oracle_dir_geom(int nside, int d, double *out /* a,b,c,sig,w,tb,tc */)
+{
+    int nd = oracle_ndirs(nside);
+    if (d < 0 || d >= nd) return -1;
+    double *n = (double *)malloc(sizeof(double) * 3 * nd);
+    oracle_directions(nside, n);
+    odir_t g;
+    dir_geom(n + 3 * d, &g);
+    free(n);
+    out[0] = g.a; out[1] = g.b; out[2] = g.c; out[3] = g.sig;
+    out[4] = g.w; out[5] = g.tb; out[6] = g.tc;
+    return 0;
+}
+
+int oracle_lattice(int nx, int ny, int nz, int nside, int d, int *range /* jlo,jhi,klo,khi */)
+{
+    int N[3] = {nx, ny, nz};
+    double geo[7];
+    if (oracle_dir_geom(nside, d, geo)) return -1;
+    odir_t g = {(int)geo[0], (int)geo[1], (int)geo[2], (int)geo[3], geo[4], geo[5], geo[6]};
+    lattice_range(&g, N, range, range + 1, range + 2, range + 3);
+    return 0;
+}
+
+int oracle_ray_segments(int nx, int ny, int nz, double h, int nside, int d, int j, int k,
+                        int *cell, double *dl, double *s0, int maxseg)
+{
+    int N[3] = {nx, ny, nz};
+    double geo[7];
+    if (oracle_dir_geom(nside, d, geo)) return -1;
+    odir_t g = {(int)geo[0], (int)geo[1], (int)geo[2], (int)geo[3], geo[4], geo[5], geo[6]};
+    int mc = max_crossings(N);
+    if (maxseg < mc) return -2;
+    double *buf = (double *)malloc(sizeof(double) * mc);
+    int ns = ray_segments(&g, N, h, j, k, buf, cell, dl, s0);
+    free(buf);
+    return ns;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The sweep (Sect. 2.2), over the directions [d_begin, d_end).             */
+/*                                                                          */
+/* Outputs (any may be NULL), cells in x-fastest order, bins outermost:     */
+/*   jin_sum[b][c] = sum_d  Ibar^{ave,in}_b(n_d, c)   (eq averaged_intensity) */
+/*   ex_sum[b][c]  = sum_d  <1 - phi>_b(n_d, c)        (reading Q4)          */
+/*   exit_sum[d][b] = sum over rays of (I_exit - I_bc)  (d indexes all N_d) */
+/*   stats[0] = number of segments with positive length (one bin)           */
+/*   stats[1] = max |w * sum_j dL_j / h - 1| over (direction, cell)         */
+/*   stats[2] = max number of crossings of one cell by one ray group        */
+/* Returns 0 on success.                                                    */
+/* ------------------------------------------------------------------------ */
+int oracle_sweep(int nx, int ny, int nz, double h, int nbins,
+                 const double *kappa, const double *S,
+                 int nside, int d_begin, int d_end, double I_bc,
+                 double *jin_sum, double *ex_sum, double *exit_sum,
+                 double *stats, int nthreads)
+{
+    const int N[3] = {nx, ny, nz};
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const int nd = oracle_ndirs(nside);
+    if (nx < 1 || ny < 1 || nz < 1 || nbins < 1 || nside < 1 || !(h > 0.0)) return -1;
+    if (d_begin < 0 || d_end > nd || d_begin > d_end) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double *n = (double *)malloc(sizeof(double) * 3 * nd);
+    oracle_directions(nside, n);
+
+    const int64_t nsc = ncell * nbins;
+    double *num = (double *)malloc(sizeof(double) * nsc);   /* sum dtau * Ibar_in */
+    double *den = (double *)malloc(sizeof(double) * nsc);   /* sum dtau */
+    double *numL = (double *)malloc(sizeof(double) * nsc);  /* sum dL * Ibar_in  (Q3) */
+    double *denL = (double *)malloc(sizeof(double) * ncell); /* sum dL */
+    double *exL = (double *)malloc(sizeof(double) * nsc);   /* sum dL * (1 - phi) (Q4) */
+    int *hits = (int *)malloc(sizeof(int) * ncell);         /* crossings per group */
+    if (!n || !num || !den || !numL || !denL || !exL || !hits) {
+        free(n); free(num); free(den); free(numL); free(denL); free(exL); free(hits);
+        return -2;
+    }
+    if (jin_sum) memset(jin_sum, 0, sizeof(double) * nsc);
+    if (ex_sum) memset(ex_sum, 0, sizeof(double) * nsc);
+    if (exit_sum) memset(exit_sum, 0, sizeof(double) * (size_t)nd * nbins);
+    double nseg_total = 0.0, inv_err = 0.0;
+    int max_hits = 0;
+    const int mc = max_crossings(N);
+
+    for (int d = d_begin; d < d_end; ++d) {
+        odir_t g;
+        dir_geom(n + 3 * d, &g);
+        memset(num, 0, sizeof(double) * nsc);
+        memset(den, 0, sizeof(double) * nsc);
+        memset(numL, 0, sizeof(double) * nsc);
+        memset(denL, 0, sizeof(double) * ncell);
+        memset(exL, 0, sizeof(double) * nsc);
+        int jlo, jhi, klo, khi;
+        lattice_range(&g, N, &jlo, &jhi, &klo, &khi);
+        const int nj = jhi - jlo + 1, nk = khi - klo + 1;
+        double *exit_d = exit_sum ? exit_sum + (size_t)d * nbins : NULL;
+
+        /* Ray groups (Sect. 3.1): rays from 2x2-interleaved lattice points. */
+        for (int grp = 0; grp < 4; ++grp) {
+            const int pj = grp & 1, pk = grp >> 1;
+            memset(hits, 0, sizeof(int) * ncell);
+            double seg_grp = 0.0;
+            int nrays = nj * nk;
+#pragma omp parallel reduction(+ : seg_grp)
+            {
+                double *buf = (double *)malloc(sizeof(double) * mc);
+                int *cell = (int *)malloc(sizeof(int) * mc);
+                double *dl = (double *)malloc(sizeof(double) * mc);
+                double *s0 = (double *)malloc(sizeof(double) * mc);
+                double *I = (double *)malloc(sizeof(double) * nbins);
+                double *exit_loc = (double *)calloc(nbins, sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+                for (int r = 0; r < nrays; ++r) {
+                    int j = jlo + r % nj, k = klo + r / nj;
+                    if ((((j % 2) + 2) % 2) != pj || (((k % 2) + 2) % 2) != pk) continue;
+                    int ns = ray_segments(&g, N, h, j, k, buf, cell, dl, s0);
+                    if (ns == 0) continue;
+                    for (int b = 0; b < nbins; ++b) I[b] = I_bc;
+                    for (int q = 0; q < ns; ++q) {
+                        const int64_t c = cell[q];
+                        hits[c] += 1;   /* rays of one group never share a cell */
+                        denL[c] += dl[q];
+                        seg_grp += 1.0;
+                        for (int b = 0; b < nbins; ++b) {
+                            const int64_t bc = (int64_t)b * ncell + c;
+                            const double dtau = kappa[bc] * dl[q];          /* eq rt */
+                            const double one_m_e = -expm1(-dtau);           /* 1 - e^{-dtau} */
+                            const double phi = dtau > 0.0 ? one_m_e / dtau : 1.0;
+                            const double ibar_in = I[b] * phi;              /* path-averaged I_in */
+                            num[bc] += dtau * ibar_in;                      /* eq averaged_intensity */
+                            den[bc] += dtau;
+                            numL[bc] += dl[q] * ibar_in;                    /* Q3 limit weights */
+                            exL[bc] += dl[q] * (1.0 - phi);                 /* Q4 */
+                            I[b] = I[b] * exp(-dtau) + S[bc] * one_m_e;     /* eq rt */
+                        }
+                    }
+                    if (exit_d)
+                        for (int b = 0; b < nbins; ++b) exit_loc[b] += I[b] - I_bc;
+                }
+                if (exit_d) {
+#pragma omp critical
+                    for (int b = 0; b < nbins; ++b) exit_d[b] += exit_loc[b];
+                }
+                free(buf); free(cell); free(dl); free(s0); free(I); free(exit_loc);
+            }
+            nseg_total += seg_grp;
+            for (int64_t c = 0; c < ncell; ++c)
+                if (hits[c] > max_hits) max_hits = hits[c];
+        }
+
+        /* Per-(direction, cell) averages, then the direction sum of eq mean_intensity. */
+        double inv_loc = 0.0;
+#pragma omp parallel for reduction(max : inv_loc)
+        for (int64_t c = 0; c < ncell; ++c) {
+            const double inv = fabs(denL[c] * g.w / h - 1.0);
+            if (inv > inv_loc) inv_loc = inv;
+            for (int b = 0; b < nbins; ++b) {
+                const int64_t bc = (int64_t)b * ncell + c;
+                double ave_in;
+                if (den[bc] > 0.0) ave_in = num[bc] / den[bc];          /* eq averaged_intensity */
+                else ave_in = denL[c] > 0.0 ? numL[bc] / denL[c] : 0.0; /* Q3 */
+                if (jin_sum) jin_sum[bc] += ave_in;
+                if (ex_sum && denL[c] > 0.0) ex_sum[bc] += exL[bc] / denL[c];
+            }
+        }
+        if (inv_loc > inv_err) inv_err = inv_loc;
+    }
+    if (stats) {
+        stats[0] = nseg_total;
+        stats[1] = inv_err;
+        stats[2] = (double)max_hits;
+    }
+    free(n); free(num); free(den); free(numL); free(denL); free(exL); free(hits);
+    return 0;
+}
