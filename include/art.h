@@ -1,0 +1,115 @@
+/*
+ * art.h -- C interface of libart, the MI355X implementation of the diffuse-
+ * radiation ray-tracing sweep of Tanaka, Yoshikawa, Okamoto & Hasegawa,
+ * "A new ray-tracing scheme for 3D diffuse radiation transfer on highly
+ * parallel architectures" (PASJ; arXiv:1410.0763), Sect. 2.2-2.3 and 3.1.
+ *
+ * The sweep: for each direction of a HEALPix set of 12 Nside^2 directions
+ * (Sect. 2.3), a lattice of parallel rays with unit spacing crosses the mesh
+ * cell by cell; across a segment of length dL the intensity becomes
+ * I e^{-dtau} + S (1 - e^{-dtau}), dtau = kappa dL (eq rt); each cell collects
+ * the optical-depth-weighted mean over the rays crossing it of the path-
+ * averaged incoming intensity I (1 - e^{-dtau}) / dtau (eqs path_averaged_
+ * intensity, averaged_intensity), and the equal-weight mean over directions is
+ * J_in, with J = J_in + S (eq mean_intensity).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Mesh fields are float32 arrays in C order [bin][z][y][x] (x fastest).
+ *   Cells are cubes of side cell_size; kappa is per unit length.
+ * - Every call returns ART_OK (0) or a negative ART_E_* code; on error the
+ *   outputs are left untouched and art_last_error() (thread-local) describes
+ *   the failure.  No C++ exception and no abort crosses this interface.
+ * - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is queued on it asynchronously unless stated otherwise; device
+ *   pointers must stay valid until the stream has passed the call.
+ * - One handle must not be used from two threads at once.
+ * - The library owns every handle and the device memory behind it.
+ */
+#ifndef ART_H
+#define ART_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ART_OK = 0,
+    ART_E_INVAL = -1,        /* bad argument (null, size, range, non-finite field) */
+    ART_E_NOMEM = -2,        /* device or host allocation failed */
+    ART_E_HIP = -3,          /* a HIP runtime call failed */
+    ART_E_STATE = -4,        /* call out of order (e.g. sweep before set_fields) */
+    ART_E_UNSUPPORTED = -5   /* valid request this build does not handle */
+};
+
+#define ART_MAX_BINS 4       /* frequency bins per mesh (Sect. 2.2 multi-bin form) */
+#define ART_MAX_NSIDE 64     /* 49152 directions */
+
+typedef struct art_mesh art_mesh;
+
+/* Caller-owned device output buffers of one sweep; any member may be NULL.
+ * J_in, J, J_exact: [nbins][cells]; Gamma: [cells]; exit_sum: [N_d][nbins]. */
+typedef struct {
+    float *J_in;     /* (1/N_d) sum_d mean of path-averaged incoming intensity */
+    float *J;        /* J_in + S  (eq mean_intensity) */
+    float *J_exact;  /* J_in + S <1 - (1 - e^{-dtau})/dtau>: the exact path
+                        average of the formal solution (eq rad_tr2) */
+    float *Gamma;    /* sum_b gamma_w[b] (J_in_b + S_b): eq gamma_diff with its
+                        frequency integral folded into the per-bin weights */
+    float *exit_sum; /* per direction and bin: sum over rays of (I_exit - I_bc) */
+} art_outputs;
+
+/* Tuning of the sweep's launch shape (see art_autotune). */
+typedef struct {
+    int bx, by, bz;   /* block of cells owned by one workgroup */
+    int subsets;      /* direction subsets per octant (workgroups per block) */
+    int threads;      /* threads per workgroup (multiple of 64, <= 1024) */
+} art_tuning;
+
+/* Create a mesh of nx*ny*nz cubic cells of side cell_size (> 0).
+ * Ownership: *out is owned by the library until art_destroy_mesh. */
+int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out);
+
+/* Release the mesh and all its device memory (NULL is accepted). */
+int art_destroy_mesh(art_mesh *mesh);
+
+/* Load the absorption coefficient kappa (>= 0, finite) and source function S
+ * (finite) of nbins frequency bins (1..ART_MAX_BINS), each [nbins][nz][ny][nx]
+ * float32, from device memory (on_device = 1) or host memory (on_device = 0).
+ * The library copies and re-lays out the data (Sect. 3: mesh data are moved to
+ * the accelerator before the sweep); the caller keeps ownership of its arrays.
+ * Synchronises hip_stream to report invalid values (ART_E_INVAL). */
+int art_set_fields(art_mesh *mesh, int nbins, const float *kappa, const float *S,
+                   int on_device, void *hip_stream);
+
+/* Full sweep over the 12 nside^2 HEALPix directions (Sect. 2.2-2.3).
+ * gamma_w: host array [nbins] of rate weights (NULL = all 1).  I_bc: uniform
+ * intensity entering the box (Sect. 3.1 casts rays from the boundaries).
+ * out: caller-owned device buffers (see art_outputs). */
+int art_sweep(art_mesh *mesh, int nside, const float *gamma_w, float I_bc,
+              const art_outputs *out, void *hip_stream);
+
+/* Raw direction sums over the HEALPix directions [d_begin, d_end) only (the
+ * direction split of Sect. 3.2): A1[b][c] = sum_d mean of the path-averaged
+ * incoming intensity, A2[b][c] = sum_d mean of (1 - (1 - e^{-dtau})/dtau),
+ * both [nbins][cells] device float32 (A2 may be NULL).  J_in = A1 / N_d after
+ * summing the ranges of all devices. */
+int art_sweep_range(art_mesh *mesh, int nside, int d_begin, int d_end, float I_bc,
+                    float *A1, float *A2, void *hip_stream);
+
+/* Launch-shape control.  art_set_tuning validates and stores t for later
+ * sweeps of this mesh (ART_E_INVAL if outside the limits, ART_E_UNSUPPORTED if
+ * the block's accumulators exceed the workgroup's local memory). */
+int art_set_tuning(art_mesh *mesh, const art_tuning *t);
+int art_get_tuning(const art_mesh *mesh, art_tuning *t);
+
+/* Number of directions of an Nside (12 nside^2), or ART_E_INVAL. */
+int art_ndirs(int nside);
+
+/* Description of the last error on this thread ("" if none). */
+const char *art_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ART_H */

@@ -1,0 +1,179 @@
+"""Python binding of libart (include/art.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP library; torch tensors serve as device
+buffers and torch streams as HIP streams.  If libart.so is missing or cannot
+be loaded, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libart.so")
+
+ART_OK = 0
+ERRORS = {-1: "ART_E_INVAL", -2: "ART_E_NOMEM", -3: "ART_E_HIP", -4: "ART_E_STATE",
+          -5: "ART_E_UNSUPPORTED"}
+MAX_BINS = 4
+MAX_NSIDE = 64
+
+# Every symbol include/art.h declares.
+EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
+           "art_sweep_range", "art_set_tuning", "art_get_tuning", "art_ndirs", "art_last_error")
+
+
+class ArtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("J_in", ctypes.c_void_p), ("J", ctypes.c_void_p), ("J_exact", ctypes.c_void_p),
+                ("Gamma", ctypes.c_void_p), ("exit_sum", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("bz", ctypes.c_int),
+                ("subsets", ctypes.c_int), ("threads", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libart.so and declare the C signatures (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libart.so not built at {path}; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, i, f, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+    L.art_create_mesh.argtypes = [i, i, i, d, ctypes.POINTER(vp)]
+    L.art_destroy_mesh.argtypes = [vp]
+    L.art_set_fields.argtypes = [vp, i, vp, vp, i, vp]
+    L.art_sweep.argtypes = [vp, i, vp, f, ctypes.POINTER(Outputs), vp]
+    L.art_sweep_range.argtypes = [vp, i, i, i, f, vp, vp, vp]
+    L.art_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.art_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.art_ndirs.argtypes = [i]
+    L.art_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "art_last_error":
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != ART_OK:
+        raise ArtError(rc, load().art_last_error().decode())
+    return rc
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def ndirs(nside: int) -> int:
+    return 12 * nside * nside
+
+
+class Mesh:
+    """A mesh of nx*ny*nz cubic cells (library-owned device state)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, cell_size: float = 1.0):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.art_create_mesh(nx, ny, nz, float(cell_size), ctypes.byref(h)))
+        self._h = h
+        self.shape = (nz, ny, nx)
+        self.nbins = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().art_destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- fields ----------------------------------------------------------
+    def set_fields(self, kappa, S, stream=None):
+        """kappa, S: float32 tensors (nbins, nz, ny, nx), CUDA or CPU."""
+        import torch
+        assert kappa.shape == S.shape and kappa.dim() == 4 and tuple(kappa.shape[1:]) == self.shape
+        kappa = kappa.contiguous()
+        S = S.contiguous()
+        assert kappa.dtype == torch.float32 and S.dtype == torch.float32
+        on_dev = 1 if kappa.is_cuda else 0
+        assert S.is_cuda == kappa.is_cuda
+        sp = _stream_ptr(stream) if on_dev else ctypes.c_void_p(0)
+        _check(load().art_set_fields(self._h, kappa.shape[0], _ptr(kappa), _ptr(S), on_dev, sp))
+        self.nbins = kappa.shape[0]
+
+    # -- tuning ----------------------------------------------------------
+    def set_tuning(self, bx, by, bz, subsets, threads):
+        t = Tuning(bx, by, bz, subsets, threads)
+        _check(load().art_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(load().art_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    # -- sweeps ----------------------------------------------------------
+    def alloc_outputs(self, nside: int, exit_sum: bool = False, device="cuda"):
+        import torch
+        nb = self.nbins
+        shp = (nb,) + self.shape
+        out = dict(J_in=torch.empty(shp, device=device), J=torch.empty(shp, device=device),
+                   J_exact=torch.empty(shp, device=device),
+                   Gamma=torch.empty(self.shape, device=device))
+        if exit_sum:
+            out["exit_sum"] = torch.empty((ndirs(nside), nb), device=device)
+        return out
+
+    def sweep(self, nside: int, gamma_w=None, I_bc: float = 0.0, out=None, exit_sum=False,
+              stream=None):
+        """Full sweep; returns (and fills) a dict of device tensors."""
+        if out is None:
+            out = self.alloc_outputs(nside, exit_sum)
+        o = Outputs(*(_ptr(out.get(k)) for k in ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
+        gw = None
+        if gamma_w is not None:
+            arr = (ctypes.c_float * self.nbins)(*[float(v) for v in gamma_w])
+            gw = ctypes.cast(arr, ctypes.c_void_p)
+        _check(load().art_sweep(self._h, nside, gw, float(I_bc), ctypes.byref(o),
+                                _stream_ptr(stream)))
+        return out
+
+    def sweep_range(self, nside: int, d_begin: int, d_end: int, I_bc: float = 0.0, A1=None,
+                    A2=None, stream=None):
+        import torch
+        shp = (self.nbins,) + self.shape
+        A1 = torch.empty(shp, device="cuda") if A1 is None else A1
+        A2 = torch.empty(shp, device="cuda") if A2 is None else A2
+        _check(load().art_sweep_range(self._h, nside, d_begin, d_end, float(I_bc), _ptr(A1),
+                                      _ptr(A2), _stream_ptr(stream)))
+        return A1, A2

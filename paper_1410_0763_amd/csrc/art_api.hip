@@ -1,0 +1,373 @@
+// art_api.hip -- host side of libart: handles, validation, buffers, the
+// block-wavefront schedule and the launch sequence of one sweep.
+//
+// Sweep = direction generator -> march launches, one per wavefront (all eight
+// octants and all direction subsets of that wavefront in one launch) ->
+// normalisation/rates -> optional exit sums.  Everything is queued on the
+// caller's stream; nothing in a sweep synchronises the host.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/art.h"
+#include "art_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? ART_E_NOMEM : ART_E_HIP,           \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+template <class T>
+int dev_alloc(T **p, size_t count, size_t *cap)
+{
+    if (*p && *cap >= count) return ART_OK;
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    if (count == 0) return ART_OK;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(ART_E_NOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                     " bytes: " + hipGetErrorString(e));
+    }
+    *cap = count;
+    return ART_OK;
+}
+
+}  // namespace
+
+struct art_mesh {
+    int nx = 0, ny = 0, nz = 0;
+    double h = 1.0;
+    long long ncell = 0;
+    int nb = 0;                         // bins loaded (0: no fields yet)
+    art_tuning tune{16, 16, 8, 2, 512};
+
+    float4 *fields = nullptr; size_t fields_cap = 0;
+    int *bad = nullptr; size_t bad_cap = 0;
+    float *stage = nullptr; size_t stage_cap = 0;   // host-upload staging
+
+    ArtDir *dirs = nullptr; size_t dirs_cap = 0;
+    int *order = nullptr; size_t order_cap = 0;
+    int *bucket_start = nullptr; size_t bs_cap = 0;
+    float *state = nullptr; size_t state_cap = 0;
+    float *acc = nullptr; size_t acc_cap = 0;
+
+    // schedule (depends on shape and tuning only)
+    ArtItem *items = nullptr; size_t items_cap = 0;
+    std::vector<int> wave_off;          // [W + 1]
+    int sched_key[6] = {0, 0, 0, 0, 0, 0};
+    ArtMeshDesc *desc = nullptr; size_t desc_cap = 0;
+    ArtMeshDesc desc_host{};
+    bool desc_valid = false;
+};
+
+namespace {
+
+int nblocks(int n, int b) { return (n + b - 1) / b; }
+
+int validate_tuning(const art_tuning &t, int nb)
+{
+    if (t.bx < 1 || t.by < 1 || t.bz < 1 || t.bx > 128 || t.by > 128 || t.bz > 128)
+        return fail(ART_E_INVAL, "tuning: block sides must be in [1, 128]");
+    if (t.subsets < 1 || t.subsets > 64) return fail(ART_E_INVAL, "tuning: subsets must be in [1, 64]");
+    if (t.threads < 64 || t.threads > 1024 || t.threads % 64)
+        return fail(ART_E_INVAL, "tuning: threads must be a multiple of 64 in [64, 1024]");
+    const long long lds = (long long)t.bx * t.by * t.bz * 2 * std::max(nb, 1) * 4;
+    if (lds > art_march_max_lds_bytes())
+        return fail(ART_E_UNSUPPORTED, "tuning: block accumulators need " + std::to_string(lds) +
+                                           " bytes of LDS, above the workgroup limit");
+    return ART_OK;
+}
+
+// Work items of the block wavefronts: launch w holds, for every octant o, the
+// blocks whose indices counted along o's travel directions sum to w, once per
+// direction subset.
+int build_schedule(art_mesh *m)
+{
+    const art_tuning &t = m->tune;
+    const int key[6] = {m->nx, m->ny, m->nz, t.bx * 1000000 + t.by * 1000 + t.bz, t.subsets, 1};
+    if (m->items && std::equal(key, key + 6, m->sched_key)) return ART_OK;
+    const int nbx = nblocks(m->nx, t.bx), nby = nblocks(m->ny, t.by), nbz = nblocks(m->nz, t.bz);
+    const int W = nbx + nby + nbz - 2;
+    std::vector<std::vector<ArtItem>> waves(W);
+    for (int o = 0; o < 8; ++o)
+        for (int r = 0; r < nbz; ++r)
+            for (int q = 0; q < nby; ++q)
+                for (int p = 0; p < nbx; ++p) {
+                    const int pp = (o & 1) ? nbx - 1 - p : p;
+                    const int qq = (o & 2) ? nby - 1 - q : q;
+                    const int rr = (o & 4) ? nbz - 1 - r : r;
+                    const int blk = (r * nby + q) * nbx + p;
+                    for (int s = 0; s < t.subsets; ++s)
+                        waves[pp + qq + rr].push_back(ArtItem{0, blk, o * t.subsets + s, 0});
+                }
+    std::vector<ArtItem> flat;
+    m->wave_off.assign(1, 0);
+    for (auto &w : waves) {
+        flat.insert(flat.end(), w.begin(), w.end());
+        m->wave_off.push_back((int)flat.size());
+    }
+    HIPCHK(hipDeviceSynchronize());   // items of earlier sweeps may still be in use
+    int rc = dev_alloc(&m->items, flat.size(), &m->items_cap);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(m->items, flat.data(), flat.size() * sizeof(ArtItem), hipMemcpyHostToDevice));
+    std::copy(key, key + 6, m->sched_key);
+    return ART_OK;
+}
+
+long long state_bound(const art_mesh *m, int nd)
+{
+    const long long N[3] = {m->nx, m->ny, m->nz};
+    long long worst = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        worst = std::max(worst, (N[b] + N[a] + 4) * (N[c] + N[a] + 4));
+    }
+    return worst * nd * m->nb;
+}
+
+// Buffers and descriptor for a sweep at this nside (allocation is the only
+// host-synchronous part, and happens only when sizes grow or tuning changes).
+int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
+{
+    const int nd = 12 * nside * nside;
+    const int nbk = 8 * m->tune.subsets;
+    int rc;
+    if ((rc = dev_alloc(&m->dirs, (size_t)nd, &m->dirs_cap))) return rc;
+    if ((rc = dev_alloc(&m->order, (size_t)nd, &m->order_cap))) return rc;
+    if ((rc = dev_alloc(&m->bucket_start, (size_t)nbk + 1, &m->bs_cap))) return rc;
+    if ((rc = dev_alloc(&m->state, (size_t)state_bound(m, nd), &m->state_cap))) return rc;
+    if ((rc = dev_alloc(&m->acc, (size_t)nbk * m->nb * 2 * m->ncell, &m->acc_cap))) return rc;
+    if ((rc = build_schedule(m))) return rc;
+    ArtMeshDesc d{};
+    d.fields = m->fields;
+    d.state = m->state;
+    d.acc = m->acc;
+    d.dirs = m->dirs;
+    d.order = m->order;
+    d.bucket_start = m->bucket_start;
+    d.ncell = m->ncell;
+    d.nx = m->nx; d.ny = m->ny; d.nz = m->nz; d.nb = m->nb;
+    d.bx = m->tune.bx; d.by = m->tune.by; d.bz = m->tune.bz;
+    d.nbx = nblocks(m->nx, d.bx); d.nby = nblocks(m->ny, d.by); d.nbz = nblocks(m->nz, d.bz);
+    d.I_bc = I_bc;
+    d.nbuckets = nbk;
+    if ((rc = dev_alloc(&m->desc, 1, &m->desc_cap))) return rc;
+    if (!m->desc_valid || std::memcmp(&d, &m->desc_host, sizeof d) != 0) {
+        // earlier sweeps queued on the stream may still read the old descriptor
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(m->desc, &d, sizeof d, hipMemcpyHostToDevice));
+        m->desc_host = d;
+        m->desc_valid = true;
+    }
+    return ART_OK;
+}
+
+int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStream_t st)
+{
+    int rc = prepare(m, nside, I_bc, st);
+    if (rc) return rc;
+    HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
+                           m->dirs, m->order, m->bucket_start, st));
+    const int lds_floats = m->tune.bx * m->tune.by * m->tune.bz * 2 * m->nb;
+    for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
+        const int n = m->wave_off[w + 1] - m->wave_off[w];
+        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, lds_floats,
+                                m->tune.threads, st));
+    }
+    return ART_OK;
+}
+
+int check_mesh_ready(const art_mesh *m, int nside)
+{
+    if (!m) return fail(ART_E_INVAL, "mesh is NULL");
+    if (m->nb == 0) return fail(ART_E_STATE, "art_set_fields has not been called");
+    if (nside < 1 || nside > ART_MAX_NSIDE)
+        return fail(ART_E_INVAL, "nside must be in [1, " + std::to_string(ART_MAX_NSIDE) + "]");
+    return ART_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *art_last_error(void) { return g_err.c_str(); }
+
+int art_ndirs(int nside)
+{
+    if (nside < 1 || nside > ART_MAX_NSIDE) return fail(ART_E_INVAL, "nside out of range");
+    return 12 * nside * nside;
+}
+
+int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out)
+{
+    try {
+        if (!out) return fail(ART_E_INVAL, "out is NULL");
+        if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+            return fail(ART_E_INVAL, "mesh sides must be in [1, 4096]");
+        if (!(cell_size > 0.0) || !std::isfinite(cell_size))
+            return fail(ART_E_INVAL, "cell_size must be positive and finite");
+        art_mesh *m = new art_mesh;
+        m->nx = nx; m->ny = ny; m->nz = nz;
+        m->h = cell_size;
+        m->ncell = (long long)nx * ny * nz;
+        *out = m;
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_destroy_mesh(art_mesh *m)
+{
+    if (!m) return ART_OK;
+    void *bufs[] = {m->fields, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
+                    m->state, m->acc, m->items, m->desc};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    delete m;
+    return ART_OK;
+}
+
+int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, int on_device,
+                   void *hip_stream)
+{
+    try {
+        if (!m || !kappa || !S) return fail(ART_E_INVAL, "null mesh or field pointer");
+        if (nbins < 1 || nbins > ART_MAX_BINS)
+            return fail(ART_E_UNSUPPORTED, "nbins must be in [1, " + std::to_string(ART_MAX_BINS) + "]");
+        int rc = validate_tuning(m->tune, nbins);
+        if (rc) return rc;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const size_t n = (size_t)m->ncell * nbins;
+        if ((rc = dev_alloc(&m->fields, n, &m->fields_cap))) return rc;
+        if ((rc = dev_alloc(&m->bad, 1, &m->bad_cap))) return rc;
+        const float *dk = kappa, *ds = S;
+        if (!on_device) {
+            if ((rc = dev_alloc(&m->stage, 2 * n, &m->stage_cap))) return rc;
+            HIPCHK(hipMemcpyAsync(m->stage, kappa, n * sizeof(float), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(m->stage + n, S, n * sizeof(float), hipMemcpyHostToDevice, st));
+            dk = m->stage;
+            ds = m->stage + n;
+        }
+        HIPCHK(hipMemsetAsync(m->bad, 0, sizeof(int), st));
+        HIPCHK(art_launch_layout(dk, ds, m->ncell, nbins, m->h, m->fields, m->bad, st));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, m->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (bad) {
+            m->nb = 0;
+            return fail(ART_E_INVAL, "kappa must be finite and >= 0 and S finite in every cell");
+        }
+        if (m->nb != nbins) m->desc_valid = false;
+        m->nb = nbins;
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_sweep(art_mesh *m, int nside, const float *gamma_w, float I_bc, const art_outputs *out,
+              void *hip_stream)
+{
+    try {
+        int rc = check_mesh_ready(m, nside);
+        if (rc) return rc;
+        if (!out) return fail(ART_E_INVAL, "outputs are NULL");
+        if (!std::isfinite(I_bc)) return fail(ART_E_INVAL, "I_bc must be finite");
+        float gw[4] = {1.f, 1.f, 1.f, 1.f};
+        if (gamma_w)
+            for (int b = 0; b < m->nb; ++b) {
+                if (!std::isfinite(gamma_w[b])) return fail(ART_E_INVAL, "gamma_w must be finite");
+                gw[b] = gamma_w[b];
+            }
+        hipStream_t st = (hipStream_t)hip_stream;
+        const int nd = 12 * nside * nside;
+        if ((rc = run_sweep(m, nside, 0, nd, I_bc, st))) return rc;
+        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
+                                    m->ncell, m->nb, nd, gw, out->J_in, out->J, out->J_exact,
+                                    out->Gamma, nullptr, nullptr, st));
+        if (out->exit_sum)
+            HIPCHK(art_launch_exit_sum(m->dirs, nd, m->state, m->nx, m->ny, m->nz, m->nb, I_bc,
+                                       out->exit_sum, st));
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_sweep_range(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, float *A1,
+                    float *A2, void *hip_stream)
+{
+    try {
+        int rc = check_mesh_ready(m, nside);
+        if (rc) return rc;
+        const int nd = 12 * nside * nside;
+        if (d_begin < 0 || d_end > nd || d_begin >= d_end)
+            return fail(ART_E_INVAL, "direction range must satisfy 0 <= d_begin < d_end <= N_d");
+        if (!A1) return fail(ART_E_INVAL, "A1 is NULL");
+        if (!std::isfinite(I_bc)) return fail(ART_E_INVAL, "I_bc must be finite");
+        hipStream_t st = (hipStream_t)hip_stream;
+        if ((rc = run_sweep(m, nside, d_begin, d_end, I_bc, st))) return rc;
+        const float ones[4] = {1.f, 1.f, 1.f, 1.f};
+        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
+                                    m->ncell, m->nb, nd, ones, nullptr, nullptr, nullptr, nullptr,
+                                    A1, A2, st));
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_set_tuning(art_mesh *m, const art_tuning *t)
+{
+    if (!m || !t) return fail(ART_E_INVAL, "null argument");
+    int rc = validate_tuning(*t, m->nb);
+    if (rc) return rc;
+    m->tune = *t;
+    m->desc_valid = false;
+    g_err.clear();
+    return ART_OK;
+}
+
+int art_get_tuning(const art_mesh *m, art_tuning *t)
+{
+    if (!m || !t) return fail(ART_E_INVAL, "null argument");
+    *t = m->tune;
+    return ART_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// art_dirs.hip -- direction set and ray-lattice generator.
+//
+// Directions are the centres of the 12 Nside^2 HEALPix pixels in RING order
+// (Sect. 2.3; Gorski et al. 2005): rings i = 1 .. 4N-1 from north to south;
+// polar-cap rings (i < N) hold 4i pixels at z = 1 - i^2/(3N^2), phi =
+// pi/(2i) (j - 1/2); belt rings (N <= i <= 3N) hold 4N pixels at
+// z = 4/3 - 2i/(3N), phi = pi/(2N) (j - s/2), s = (i - N + 1) mod 2 (pixels of
+// rings with s = 0 numbered from phi = 0); the south cap mirrors the north.
+//
+// For each direction the generator fixes the parallel-ray lattice of Sect. 2.2
+// (rays at the half-integer points of the upstream face of the dominant axis,
+// unit spacing; ties of the dominant axis go to the lowest axis index within
+// 1e-12; components below 1e-12 are zero), the octant of travel, the workgroup
+// bucket (octant x subset) and the offset of its rays in the state buffer.
+//
+// One workgroup: every thread builds directions; wave 0 then assigns buckets
+// and offsets with wave-wide prefix sums, so the result is deterministic.
+#include "art_internal.h"
+
+#define ART_TIE 1e-12
+
+namespace {
+
+__device__ void healpix_ring(int nside, int d, double *n)
+{
+    const double N = (double)nside;
+    const double PI = 3.14159265358979323846;
+    int i = 1, start = 0;
+    // walk the rings until the one holding pixel d
+    for (;; ++i) {
+        int npix = (i < nside) ? 4 * i : (i <= 3 * nside ? 4 * nside : 4 * (4 * nside - i));
+        if (d < start + npix) break;
+        start += npix;
+    }
+    const int j = d - start + 1;   // 1-based position in the ring
+    double z, phi;
+    if (i < nside) {
+        z = 1.0 - (double)i * i / (3.0 * N * N);
+        phi = PI / (2.0 * i) * (j - 0.5);
+    } else if (i <= 3 * nside) {
+        z = 4.0 / 3.0 - 2.0 * i / (3.0 * N);
+        const int s = (i - nside + 1) % 2;
+        phi = PI / (2.0 * N) * (s ? (j - 0.5) : (double)(j - 1));
+    } else {
+        const int ip = 4 * nside - i;
+        z = -(1.0 - (double)ip * ip / (3.0 * N * N));
+        phi = PI / (2.0 * ip) * (j - 0.5);
+    }
+    const double st = sqrt((1.0 - z) * (1.0 + z));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    n[0] = st * cp;
+    n[1] = st * sp;
+    n[2] = z;
+    for (int q = 0; q < 3; ++q)
+        if (fabs(n[q]) < ART_TIE) n[q] = 0.0;
+}
+
+__device__ void build_dir(int nside, int d, int nx, int ny, int nz, ArtDir *out)
+{
+    double n[3];
+    healpix_ring(nside, d, n);
+    const int N[3] = {nx, ny, nz};
+    const double m = fmax(fabs(n[0]), fmax(fabs(n[1]), fabs(n[2])));
+    const int a = fabs(n[0]) >= m - ART_TIE ? 0 : (fabs(n[1]) >= m - ART_TIE ? 1 : 2);
+    const int b = (a == 0) ? 1 : 0;
+    const int c = (a == 2) ? 1 : 2;
+    const double w = fabs(n[a]);
+    ArtDir D;
+    D.n[0] = n[0]; D.n[1] = n[1]; D.n[2] = n[2];
+    D.a = a; D.b = b; D.c = c;
+    D.w = w;
+    D.invw = 1.0 / w;
+    const double sig = n[a] > 0.0 ? 1.0 : -1.0;
+    D.alpha_a = sig > 0.0 ? 0.0 : (double)N[a];
+    const double tb = n[b] / w, tc = n[c] / w;
+    for (int q = 0; q < 3; ++q) {
+        const double bq = (q == a) ? sig : (q == b ? tb : tc);
+        D.beta[q] = bq;
+        D.rbeta[q] = bq != 0.0 ? 1.0 / bq : 0.0;
+    }
+    D.octant = (D.beta[0] < 0.0 ? 1 : 0) | (D.beta[1] < 0.0 ? 2 : 0) | (D.beta[2] < 0.0 ? 4 : 0);
+    // lattice: x_b = j + 1/2 + tb s must meet (0, N_b) for some s in [0, N_a]
+    const double Na = (double)N[a];
+    const int jlo = (int)floor(-0.5 - fmax(0.0, tb * Na));
+    const int jhi = (int)ceil((double)N[b] - 0.5 - fmin(0.0, tb * Na));
+    const int klo = (int)floor(-0.5 - fmax(0.0, tc * Na));
+    const int khi = (int)ceil((double)N[c] - 0.5 - fmin(0.0, tc * Na));
+    D.j0 = jlo; D.nj = jhi - jlo + 1;
+    D.k0 = klo; D.nk = khi - klo + 1;
+    D.state_off = 0;
+    D.bucket = -1;
+    D.pad = 0;
+    *out = D;
+}
+
+__global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny, int nz, int nb,
+                                                       int d_begin, int d_end, int subsets,
+                                                       ArtDir *__restrict__ dirs,
+                                                       int *__restrict__ order,
+                                                       int *__restrict__ bucket_start)
+{
+    const int nd = 12 * nside * nside;
+    for (int d = threadIdx.x; d < nd; d += blockDim.x) build_dir(nside, d, nx, ny, nz, dirs + d);
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+
+    // Wave 0: rank of each in-range direction within its octant (ballot
+    // prefix counts in index order), bucket = octant * subsets + rank % subsets,
+    // and the state-buffer offsets (prefix sum of nj * nk * nb).
+    const int lane = threadIdx.x;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int oct_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long off_base = 0;
+    for (int base = 0; base < nd; base += 64) {
+        const int d = base + lane;
+        const bool valid = d < nd && d >= d_begin && d < d_end;
+        const int oct = (d < nd) ? dirs[d].octant : -1;
+        int rank = 0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const unsigned long long msk = __ballot(valid && oct == o);
+            if (valid && oct == o) rank = oct_count[o] + __popcll(msk & below);
+            oct_count[o] += __popcll(msk);
+        }
+        long long mine = valid ? (long long)dirs[d].nj * dirs[d].nk * nb : 0;
+        long long incl = mine;
+        for (int sh = 1; sh < 64; sh <<= 1) {
+            const long long t = __shfl_up(incl, sh, 64);
+            if (lane >= sh) incl += t;
+        }
+        if (d < nd) {
+            dirs[d].state_off = off_base + incl - mine;
+            dirs[d].bucket = valid ? oct * subsets + rank % subsets : -1;
+            dirs[d].pad = valid ? rank / subsets : 0;   // position inside the bucket
+        }
+        off_base += __shfl(incl, 63, 64);
+    }
+    // Bucket sizes follow from the octant counts (identical in every lane),
+    // so each lane derives the bucket offsets itself.
+    auto bucket_size = [&](int bk) {
+        const int o = bk / subsets, s = bk % subsets;
+        return (oct_count[o] > s) ? (oct_count[o] - s + subsets - 1) / subsets : 0;
+    };
+    if (lane == 0) {
+        int acc = 0;
+        for (int bk = 0; bk < 8 * subsets; ++bk) {
+            bucket_start[bk] = acc;
+            acc += bucket_size(bk);
+        }
+        bucket_start[8 * subsets] = acc;
+    }
+    for (int d = lane; d < nd; d += 64) {
+        const int bk = dirs[d].bucket;   // written by this lane above
+        if (bk < 0) continue;
+        int start = 0;
+        for (int q = 0; q < bk; ++q) start += bucket_size(q);
+        order[start + dirs[d].pad] = d;
+    }
+}
+
+}  // namespace
+
+hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start,
+                           hipStream_t stream)
+{
+    hipLaunchKernelGGL(art_dirs_kernel, dim3(1), dim3(256), 0, stream, nside, nx, ny, nz, nb,
+                       d_begin, d_end, subsets, dirs, order, bucket_start);
+    return hipGetLastError();
+}

@@ -1,0 +1,143 @@
+// art_fields.hip -- field layout, normalisation / rates, exit sums.
+//
+// Layout (at set_fields): kappa and S arrive as [bin][cell]; the march wants
+// all bins of a cell in one place, so each cell gets nb float4 records
+// {kappa h, 1/(kappa h), S, 0} (kappa h is the optical depth per cell length).
+//
+// Normalisation (Sect. 2.2, eq mean_intensity, and eq gamma_diff):
+//   J_in = A1 / N_d,  J = J_in + S,  J_exact = J_in + S A2 / N_d,
+//   Gamma = sum_b g_b (J_in_b + S_b),
+// where A1, A2 are summed over the per-bucket accumulator copies in a fixed
+// order (deterministic).  Copies of empty buckets are skipped.
+//
+// Exit sums: after a sweep every ray's state slot holds the intensity with
+// which it left the mesh; one workgroup per direction adds up I_exit - I_bc
+// over the rays that cross the mesh (photon-balance diagnostics).
+#include "art_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void art_layout_kernel(const float *__restrict__ kappa,
+                                                         const float *__restrict__ S,
+                                                         long long ncell, int nb, float h,
+                                                         float4 *__restrict__ fields,
+                                                         int *__restrict__ bad)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    for (int b = 0; b < nb; ++b) {
+        const float k = kappa[(long long)b * ncell + c];
+        const float s = S[(long long)b * ncell + c];
+        if (!(k >= 0.0f) || !isfinite(k) || !isfinite(s)) *bad = 1;
+        const float kh = k * h;
+        fields[c * nb + b] = make_float4(kh, kh > 0.0f ? 1.0f / kh : INFINITY, s, 0.0f);
+    }
+}
+
+struct GW {
+    float g[4];
+};
+
+__global__ __launch_bounds__(256) void art_normalize_kernel(
+    const float *__restrict__ acc, const int *__restrict__ bucket_start, int nbuckets,
+    const float4 *__restrict__ fields, long long ncell, int nb, float inv_nd, GW gw,
+    float *__restrict__ J_in, float *__restrict__ J, float *__restrict__ J_exact,
+    float *__restrict__ Gamma, float *__restrict__ A1raw, float *__restrict__ A2raw)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    float gam = 0.0f;
+    for (int b = 0; b < nb; ++b) {
+        float a1 = 0.0f, a2 = 0.0f;
+        for (int k = 0; k < nbuckets; ++k) {
+            if (bucket_start[k + 1] == bucket_start[k]) continue;
+            const float *base = acc + ((long long)k * nb + b) * 2 * ncell;
+            a1 += base[c];
+            a2 += base[ncell + c];
+        }
+        const long long bc = (long long)b * ncell + c;
+        if (A1raw) A1raw[bc] = a1;
+        if (A2raw) A2raw[bc] = a2;
+        const float s = fields[c * nb + b].z;
+        const float jin = a1 * inv_nd;
+        if (J_in) J_in[bc] = jin;
+        if (J) J[bc] = jin + s;
+        if (J_exact) J_exact[bc] = fmaf(s, a2 * inv_nd, jin);
+        gam = fmaf(gw.g[b], jin + s, gam);
+    }
+    if (Gamma) Gamma[c] = gam;
+}
+
+__global__ __launch_bounds__(256) void art_exit_sum_kernel(const ArtDir *__restrict__ dirs,
+                                                           const float *__restrict__ state, int nx,
+                                                           int ny, int nz, int nb, float I_bc,
+                                                           float *__restrict__ exit_sum)
+{
+    __shared__ float red[4][256];
+    const int d = blockIdx.x;
+    const ArtDir D = dirs[d];
+    float sum[4] = {0.f, 0.f, 0.f, 0.f};
+    if (D.bucket >= 0) {
+        const double N[3] = {(double)nx, (double)ny, (double)nz};
+        const int nr = D.nj * D.nk;
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+            const int j = D.j0 + r % D.nj, k = D.k0 + r / D.nj;
+            double lo = -INFINITY, hi = INFINITY;
+            bool ok = true;
+            for (int q = 0; q < 3; ++q) {
+                const double x0 = q == D.a ? D.alpha_a : (q == D.b ? j + 0.5 : k + 0.5);
+                if (D.beta[q] == 0.0) {
+                    ok = ok && (x0 > 0.0 && x0 < N[q]);
+                } else {
+                    const double t0 = (0.0 - x0) * D.rbeta[q], t1 = (N[q] - x0) * D.rbeta[q];
+                    lo = fmax(lo, fmin(t0, t1));
+                    hi = fmin(hi, fmax(t0, t1));
+                }
+            }
+            if (!ok || !(hi > lo)) continue;
+            const long long sidx = D.state_off + ((long long)r) * nb;
+            for (int b = 0; b < nb; ++b) sum[b] += state[sidx + b] - I_bc;
+        }
+    }
+    for (int b = 0; b < 4; ++b) red[b][threadIdx.x] = sum[b];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int b = 0; b < 4; ++b) red[b][threadIdx.x] += red[b][threadIdx.x + w];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < nb) exit_sum[(long long)d * nb + threadIdx.x] = red[threadIdx.x][0];
+}
+
+}  // namespace
+
+hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
+                             double h, float4 *fields, int *bad_flag, hipStream_t stream)
+{
+    const long long nblk = (ncell + 255) / 256;
+    hipLaunchKernelGGL(art_layout_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, kappa, S,
+                       ncell, nb, (float)h, fields, bad_flag);
+    return hipGetLastError();
+}
+
+hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
+                                const float4 *fields, long long ncell, int nb, int nd,
+                                const float *gw4, float *J_in, float *J, float *J_exact,
+                                float *Gamma, float *A1raw, float *A2raw, hipStream_t stream)
+{
+    GW gw;
+    for (int b = 0; b < 4; ++b) gw.g[b] = gw4[b];
+    const long long nblk = (ncell + 255) / 256;
+    hipLaunchKernelGGL(art_normalize_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, acc,
+                       bucket_start, nbuckets, fields, ncell, nb, 1.0f / (float)nd, gw, J_in, J,
+                       J_exact, Gamma, A1raw, A2raw);
+    return hipGetLastError();
+}
+
+hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
+                               int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream)
+{
+    hipLaunchKernelGGL(art_exit_sum_kernel, dim3(nd), dim3(256), 0, stream, dirs, state, nx, ny,
+                       nz, nb, I_bc, exit_sum);
+    return hipGetLastError();
+}

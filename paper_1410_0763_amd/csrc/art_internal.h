@@ -1,0 +1,67 @@
+// art_internal.h -- data structures shared by the HIP kernels and the host
+// side of libart.  Not part of the public interface (include/art.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+// One direction of the HEALPix set with its parallel-ray lattice (Sect. 2.2,
+// 2.3).  Ray (j,k) is the line x_i(s) = alpha_i + beta_i s over depth s in
+// [0, N_a]: along the dominant axis a, alpha_a is the upstream face (0 or N_a)
+// and beta_a = +-1; along the transverse axes b < c, alpha = j + 1/2 (or
+// k + 1/2) and beta = n_b/|n_a| (n_c/|n_a|).  World axes are x = 0, y = 1, z = 2.
+struct ArtDir {
+    double n[3];          // unit direction
+    double alpha_a;       // x_a at depth 0
+    double beta[3];       // dx_i/ds per world axis
+    double rbeta[3];      // 1/beta_i (0 where beta_i = 0)
+    double w;             // |n_a|: one unit of depth is a path of 1/w cells
+    double invw;          // 1/|n_a|
+    int a, b, c;          // dominant axis, then the other two (b < c)
+    int octant;           // bit i set: the rays travel towards decreasing x_i
+    int j0, nj, k0, nk;   // lattice index ranges [j0, j0+nj) x [k0, k0+nk)
+    long long state_off;  // first float of this direction's ray states
+    int bucket;           // octant * subsets + subset; -1 outside the range
+    int pad;
+};
+
+// Everything one workgroup of the march needs about its mesh.
+struct ArtMeshDesc {
+    const float4 *fields;      // [cell][nb] = {kappa h, 1/(kappa h), S, 0}
+    float *state;              // ray intensities handed from block to block
+    float *acc;                // [bucket][nb][2][cell] per-bucket direction sums
+    const ArtDir *dirs;        // [N_d]
+    const int *order;          // direction indices grouped by bucket
+    const int *bucket_start;   // [nbuckets + 1]
+    long long ncell;
+    int nx, ny, nz, nb;
+    int bx, by, bz;            // block shape
+    int nbx, nby, nbz;         // blocks per axis
+    float I_bc;
+    int nbuckets;
+};
+
+// Work item of one wavefront launch: (mesh, block, bucket).
+struct ArtItem {
+    int mesh;
+    int block;                 // linear block index (x fastest)
+    int bucket;
+    int pad;
+};
+
+#define ART_CHECK_LAUNCH() (hipGetLastError())
+
+// Kernel launchers (defined in the .hip files).
+hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start,
+                           hipStream_t stream);
+hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes,
+                            int lds_floats, int threads, hipStream_t stream);
+hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
+                             double h, float4 *fields, int *bad_flag, hipStream_t stream);
+hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
+                                const float4 *fields, long long ncell, int nb, int nd,
+                                const float *gw4, float *J_in, float *J, float *J_exact,
+                                float *Gamma, float *A1raw, float *A2raw, hipStream_t stream);
+hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
+                               int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
+int art_march_max_lds_bytes();
