@@ -1,0 +1,152 @@
+"""Benchmark of the diffuse-radiation sweep on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one full sweep (direction generator, block-wavefront march,
+normalisation and rates) of the 256^3 clumpy workload: lognormal density with
+sigma_ln = 1.5 and 64 opaque spheres, HEALPix nside 8 (768 directions), four
+frequency bins, fields resident in HBM before timing starts.  One JSON line is
+printed; `value` is segment-bin updates per second (one ray-cell segment of
+positive length in one frequency bin), counted by the kernels themselves.
+
+roofline: algorithmic bytes of the march = 8 B (kappa_b and S_b read once) per
+(cell, direction, bin), divided by the march phase's HIP-event time on the
+sweep's stream, against the 8 TB/s HBM peak; `traffic` is the HBM byte count
+of the march from the committed rocprofv3 counter summary, null when that
+summary was taken on a different march kernel source.
+
+cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
+bounded sample of the same workload: two of the 768 directions over the full
+mesh and all four bins.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("plain_256: 256^3 lognormal (sigma_ln 1.5) + 64 spheres (kappa x100), "
+            "HEALPix nside 8 (768 directions), 4 frequency bins, FP32")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_plain_256_traffic.json")
+MARCH_SRC = os.path.join(ROOT, "paper_1410_0763_amd", "csrc", "art_march.hip")
+
+
+def march_source_hash():
+    with open(MARCH_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(nlaunch_bytes_scale):
+    """HBM bytes per sweep of the march from the committed counter summary,
+    or None when absent or taken on another march source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("march_source_sha256_16") != march_source_hash():
+        return None
+    return t.get("hbm_bytes_per_sweep")
+
+
+def cpu_baseline(medium, d_range=(384, 386)):
+    import numpy as np
+    from oracle import oracle as O
+    threads = min(16, os.cpu_count() or 1)
+    k = medium.kappa.astype(np.float64)
+    s = medium.S.astype(np.float64)
+    t0 = time.perf_counter()
+    r = O.sweep_raw(k, s, medium.nside, d_range=d_range, nthreads=threads)
+    dt = time.perf_counter() - t0
+    units = r["nseg"] * medium.nbins
+    return {"value": units / dt, "unit": "seg-bin updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"directions {d_range[0]}..{d_range[1] - 1} of 768, full 256^3 mesh, "
+                      f"4 bins ({units:.3e} segment-bin updates in {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the sweep of one mesh is measured on one MI355X; "
+              "see DESIGN.md for how directions would be sharded across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1410_0763_amd import art, media
+
+    torch.cuda.set_device(0)
+    m = media.plain_256()
+    nb, nz, ny, nx = m.kappa.shape
+    mesh = art.Mesh(nx, ny, nz, m.cell_size)
+    mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+    out = mesh.alloc_outputs(m.nside)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        mesh.sweep(m.nside, gamma_w=m.gamma_w, out=out)
+    torch.cuda.synchronize()
+
+    march_ms, sweep_ms, segs = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mesh.sweep(m.nside, gamma_w=m.gamma_w, out=out)
+        st = mesh.stats()          # waits for this sweep's end event
+        march_ms.append(st["march_ms"])
+        sweep_ms.append(st["sweep_ms"])
+        segs.append(st["segments"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    seg_bins = segs[-1] * nb
+    ms_per_step = 1e3 * wall / args.steps
+    value = seg_bins / (sum(sweep_ms) / len(sweep_ms) / 1e3)
+    nd = 12 * m.nside ** 2
+    alg_bytes = 8.0 * nx * ny * nz * nd * nb
+    march_s = (sum(march_ms) / len(march_ms)) / 1e3
+    achieved = alg_bytes / march_s / 1e9
+    traffic = load_traffic(None)
+    rec = {
+        "metric": "ray-segment updates/s (segment-bin updates per second) of the plain FP32 sweep",
+        "value": value,
+        "unit": "seg-bin updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "mesh": [nx, ny, nz], "nside": m.nside, "nbins": nb,
+                   "directions": nd, "tuning": mesh.get_tuning(),
+                   "segments_per_bin": segs[-1], "sweep_ms_event": sum(sweep_ms) / len(sweep_ms),
+                   "march_ms_event": sum(march_ms) / len(march_ms)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_sweep": alg_bytes,
+                     "kernel": "art_march_kernel<4> (all wavefront launches of one sweep)"},
+        "cpu_baseline": None,
+    }
+    mesh.close()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(m)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,15 @@ int art_sweep(art_mesh *mesh, int nside, const float *gamma_w, float I_bc,
 int art_sweep_range(art_mesh *mesh, int nside, int d_begin, int d_end, float I_bc,
                     float *A1, float *A2, void *hip_stream);
 
+/* Work and time of the last sweep of this mesh (synchronises with it):
+ * segments = ray-cell segments of positive length marched (per bin; the work
+ * unit of one bin is one segment update), march_ms = time from the first to
+ * the end of the last march launch, sweep_ms = time from the direction
+ * generator to the end of the rates; both from HIP events recorded on the
+ * sweep's stream.  Any pointer may be NULL.
+ * ART_E_STATE if no sweep has run. */
+int art_sweep_stats(art_mesh *mesh, long long *segments, float *march_ms, float *sweep_ms);
+
 /* Launch-shape control.  art_set_tuning validates and stores t for later
  * sweeps of this mesh (ART_E_INVAL if outside the limits, ART_E_UNSUPPORTED if
  * the block's accumulators exceed the workgroup's local memory). */

@@ -20,7 +20,8 @@ MAX_NSIDE = 64
 
 # Every symbol include/art.h declares.
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
-           "art_sweep_range", "art_set_tuning", "art_get_tuning", "art_ndirs", "art_last_error")
+           "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning", "art_ndirs",
+           "art_last_error")
 
 
 class ArtError(RuntimeError):
@@ -59,6 +60,8 @@ def load(path: str = LIB_PATH):
     L.art_set_fields.argtypes = [vp, i, vp, vp, i, vp]
     L.art_sweep.argtypes = [vp, i, vp, f, ctypes.POINTER(Outputs), vp]
     L.art_sweep_range.argtypes = [vp, i, i, i, f, vp, vp, vp]
+    L.art_sweep_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.art_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.art_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.art_ndirs.argtypes = [i]
@@ -167,6 +170,15 @@ class Mesh:
         _check(load().art_sweep(self._h, nside, gw, float(I_bc), ctypes.byref(o),
                                 _stream_ptr(stream)))
         return out
+
+    def stats(self) -> dict:
+        """Segments marched (per bin) and event times of the last sweep (synchronises)."""
+        seg = ctypes.c_longlong()
+        mms = ctypes.c_float()
+        sms = ctypes.c_float()
+        _check(load().art_sweep_stats(self._h, ctypes.byref(seg), ctypes.byref(mms),
+                                      ctypes.byref(sms)))
+        return dict(segments=seg.value, march_ms=mms.value, sweep_ms=sms.value)
 
     def sweep_range(self, nside: int, d_begin: int, d_end: int, I_bc: float = 0.0, A1=None,
                     A2=None, stream=None):

@@ -75,6 +75,9 @@ struct art_mesh {
 
     // schedule (depends on shape and tuning only)
     ArtItem *items = nullptr; size_t items_cap = 0;
+    unsigned int *seg_count = nullptr; size_t seg_cap = 0;   // per work item
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, march start, march end, end
+    bool timed = false;
     std::vector<int> wave_off;          // [W + 1]
     int sched_key[6] = {0, 0, 0, 0, 0, 0};
     ArtMeshDesc *desc = nullptr; size_t desc_cap = 0;
@@ -93,7 +96,7 @@ int validate_tuning(const art_tuning &t, int nb)
     if (t.subsets < 1 || t.subsets > 64) return fail(ART_E_INVAL, "tuning: subsets must be in [1, 64]");
     if (t.threads < 64 || t.threads > 1024 || t.threads % 64)
         return fail(ART_E_INVAL, "tuning: threads must be a multiple of 64 in [64, 1024]");
-    const long long lds = (long long)t.bx * t.by * t.bz * 2 * std::max(nb, 1) * 4;
+    const long long lds = (long long)art_march_lds_floats(t.bx, t.by, t.bz, std::max(nb, 1)) * 4;
     if (lds > art_march_max_lds_bytes())
         return fail(ART_E_UNSUPPORTED, "tuning: block accumulators need " + std::to_string(lds) +
                                            " bytes of LDS, above the workgroup limit");
@@ -131,6 +134,7 @@ int build_schedule(art_mesh *m)
     HIPCHK(hipDeviceSynchronize());   // items of earlier sweeps may still be in use
     int rc = dev_alloc(&m->items, flat.size(), &m->items_cap);
     if (rc) return rc;
+    if ((rc = dev_alloc(&m->seg_count, flat.size(), &m->seg_cap))) return rc;
     HIPCHK(hipMemcpy(m->items, flat.data(), flat.size() * sizeof(ArtItem), hipMemcpyHostToDevice));
     std::copy(key, key + 6, m->sched_key);
     return ART_OK;
@@ -188,14 +192,19 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
 {
     int rc = prepare(m, nside, I_bc, st);
     if (rc) return rc;
+    if (!m->ev[0])
+        for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&m->ev[i]));
+    HIPCHK(hipEventRecord(m->ev[0], st));
     HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
                            m->dirs, m->order, m->bucket_start, st));
-    const int lds_floats = m->tune.bx * m->tune.by * m->tune.bz * 2 * m->nb;
+    HIPCHK(hipEventRecord(m->ev[1], st));
+    const int lds_floats = art_march_lds_floats(m->tune.bx, m->tune.by, m->tune.bz, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
         const int n = m->wave_off[w + 1] - m->wave_off[w];
-        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, lds_floats,
-                                m->tune.threads, st));
+        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, lds_floats,
+                                m->tune.threads, m->seg_count + m->wave_off[w], st));
     }
+    HIPCHK(hipEventRecord(m->ev[2], st));
     return ART_OK;
 }
 
@@ -246,7 +255,9 @@ int art_destroy_mesh(art_mesh *m)
 {
     if (!m) return ART_OK;
     void *bufs[] = {m->fields, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
-                    m->state, m->acc, m->items, m->desc};
+                    m->state, m->acc, m->items, m->desc, m->seg_count};
+    for (hipEvent_t e : m->ev)
+        if (e) (void)hipEventDestroy(e);
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     delete m;
@@ -314,6 +325,8 @@ int art_sweep(art_mesh *m, int nside, const float *gamma_w, float I_bc, const ar
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, gw, out->J_in, out->J, out->J_exact,
                                     out->Gamma, nullptr, nullptr, st));
+        HIPCHK(hipEventRecord(m->ev[3], st));
+        m->timed = true;
         if (out->exit_sum)
             HIPCHK(art_launch_exit_sum(m->dirs, nd, m->state, m->nx, m->ny, m->nz, m->nb, I_bc,
                                        out->exit_sum, st));
@@ -343,6 +356,8 @@ int art_sweep_range(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, 
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, ones, nullptr, nullptr, nullptr, nullptr,
                                     A1, A2, st));
+        HIPCHK(hipEventRecord(m->ev[3], st));
+        m->timed = true;
         g_err.clear();
         return ART_OK;
     } catch (const std::bad_alloc &) {
@@ -361,6 +376,29 @@ int art_set_tuning(art_mesh *m, const art_tuning *t)
     m->desc_valid = false;
     g_err.clear();
     return ART_OK;
+}
+
+int art_sweep_stats(art_mesh *m, long long *segments, float *march_ms, float *sweep_ms)
+{
+    try {
+        if (!m) return fail(ART_E_INVAL, "mesh is NULL");
+        if (!m->timed) return fail(ART_E_STATE, "no sweep has run on this mesh");
+        HIPCHK(hipEventSynchronize(m->ev[3]));
+        if (march_ms) HIPCHK(hipEventElapsedTime(march_ms, m->ev[1], m->ev[2]));
+        if (sweep_ms) HIPCHK(hipEventElapsedTime(sweep_ms, m->ev[0], m->ev[3]));
+        if (segments) {
+            const size_t n = (size_t)m->wave_off.back();
+            std::vector<unsigned int> h(n);
+            HIPCHK(hipMemcpy(h.data(), m->seg_count, n * sizeof(unsigned int), hipMemcpyDeviceToHost));
+            long long tot = 0;
+            for (unsigned int v : h) tot += v;
+            *segments = tot;
+        }
+        g_err.clear();
+        return ART_OK;
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
 }
 
 int art_get_tuning(const art_mesh *m, art_tuning *t)

@@ -54,8 +54,9 @@ struct ArtItem {
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
                            int subsets, ArtDir *dirs, int *order, int *bucket_start,
                            hipStream_t stream);
-hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes,
-                            int lds_floats, int threads, hipStream_t stream);
+hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
+                            int lds_floats, int threads, unsigned int *seg_count,
+                            hipStream_t stream);
 hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
                              double h, float4 *fields, int *bad_flag, hipStream_t stream);
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
@@ -65,3 +66,4 @@ hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int n
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
 int art_march_max_lds_bytes();
+int art_march_lds_floats(int bx, int by, int bz, int nb);

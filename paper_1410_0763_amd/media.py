@@ -45,7 +45,7 @@ def gaussian_random_field(shape, seed: int, slope: float = -3.0) -> np.ndarray:
     amp = np.zeros_like(k2)
     nz_mask = k2 > 0
     amp[nz_mask] = k2[nz_mask] ** (slope / 4.0)  # sqrt(P) = k^(slope/2)
-    g = np.fft.irfftn(fk * amp, s=(nz, ny, nx))
+    g = np.fft.irfftn(fk * amp, s=(nz, ny, nx), axes=(0, 1, 2))
     g -= g.mean()
     sd = g.std()
     if sd > 0:
