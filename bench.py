@@ -16,8 +16,8 @@ of the march from the committed rocprofv3 counter summary, null when that
 summary was taken on a different march kernel source.
 
 cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
-bounded sample of the same workload: two of the 768 directions over the full
-mesh and all four bins.
+bounded sample of the same workload: 24 of the 768 directions (around the
+equator) over the full mesh and all four bins.
 """
 from __future__ import annotations
 
@@ -56,7 +56,60 @@ def load_traffic(nlaunch_bytes_scale):
     return t.get("hbm_bytes_per_sweep")
 
 
-def cpu_baseline(medium, d_range=(384, 386)):
+COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size, run under the same
+    FETCH_SIZE / WRITE_SIZE counters as the march to calibrate them."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
+
+
+def _pmc_sums(csv_path, counter):
+    """Per-kernel-name sums of one counter over all dispatches (KiB as reported)."""
+    import csv
+    import collections
+    out = collections.defaultdict(float)
+    calls = collections.Counter()
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            out[r["Kernel_Name"]] += float(r["Counter_Value"])
+            calls[r["Kernel_Name"]] += 1
+    return out, calls
+
+
+def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sweeps):
+    """HBM bytes per sweep of the march from FETCH_SIZE and WRITE_SIZE runs,
+    each scaled by what the same counter reads for the calibration copy."""
+    f, fc = _pmc_sums(fetch_csv, "FETCH_SIZE")
+    w, _ = _pmc_sums(write_csv, "WRITE_SIZE")
+    cf, _ = _pmc_sums(copy_fetch_csv, "FETCH_SIZE")
+    cw, _ = _pmc_sums(copy_write_csv, "WRITE_SIZE")
+    ckey = max(cf, key=cf.get)                   # the copy kernel
+    fetch_scale = COPY_BYTES / (cf[ckey] * 1024.0)
+    write_scale = COPY_BYTES / (cw[ckey] * 1024.0)
+    mk = [k for k in f if "art_march_kernel" in k]
+    fetch = sum(f[k] for k in mk) * 1024.0 * fetch_scale / sweeps
+    write = sum(w.get(k, 0.0) for k in mk) * 1024.0 * write_scale / sweeps
+    rec = {"kernel": mk, "dispatches": sum(fc[k] for k in mk), "sweeps": sweeps,
+           "fetch_bytes_per_sweep": fetch, "write_bytes_per_sweep": write,
+           "hbm_bytes_per_sweep": fetch + write,
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "march_source_sha256_16": march_source_hash()}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(medium, d_range=(372, 396)):
     import numpy as np
     from oracle import oracle as O
     threads = min(16, os.cpu_count() or 1)
@@ -77,7 +130,19 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only the counter-calibration copy of 1 GiB")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                        "COPY_WRITE_CSV"),
+                    help="write the march traffic summary from rocprofv3 --pmc CSVs")
+    ap.add_argument("--sweeps", type=int, default=1, help="sweeps in the --traffic-from runs")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from, sweeps=args.sweeps)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the sweep of one mesh is measured on one MI355X; "
               "see DESIGN.md for how directions would be sharded across GPUs.", file=sys.stderr)

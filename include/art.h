@@ -59,11 +59,15 @@ typedef struct {
     float *exit_sum; /* per direction and bin: sum over rays of (I_exit - I_bc) */
 } art_outputs;
 
-/* Tuning of the sweep's launch shape (see art_autotune). */
+/* Launch shape of the sweep.  For directions with dominant axis a the mesh is
+ * cut into blocks of 8 x 8 columns (the two other axes) by `depth` cells
+ * along a; one workgroup of `waves` 64-lane waves marches one block for one
+ * bucket of directions (one of `subsets` parts of a dominant-axis x octant
+ * group). */
 typedef struct {
-    int bx, by, bz;   /* block of cells owned by one workgroup */
-    int subsets;      /* direction subsets per octant (workgroups per block) */
-    int threads;      /* threads per workgroup (multiple of 64, <= 1024) */
+    int depth;        /* cells of a block along the dominant axis, 1..256 */
+    int subsets;      /* buckets per (dominant axis, octant) group, 1..64 */
+    int waves;        /* waves per workgroup, 1..16 */
 } art_tuning;
 
 /* Create a mesh of nx*ny*nz cubic cells of side cell_size (> 0).
@@ -111,6 +115,26 @@ int art_sweep_stats(art_mesh *mesh, long long *segments, float *march_ms, float 
  * the block's accumulators exceed the workgroup's local memory). */
 int art_set_tuning(art_mesh *mesh, const art_tuning *t);
 int art_get_tuning(const art_mesh *mesh, art_tuning *t);
+
+/* Batched form: one launch sequence for n distinct meshes (each already
+ * holding fields, each with its own shape, Nside, bins and tuning), captured
+ * once into a HIP graph.  Launch w of the sequence marches wavefront w of
+ * every mesh.  nside[i], gamma_w[i] (host array of the mesh's bins, or NULL),
+ * outs[i] (caller-owned device buffers, which must outlive the batch) as in
+ * art_sweep; exit sums are not produced (outs[i].exit_sum is ignored).  waves:
+ * waves per workgroup for all meshes, 1..16.  art_batch_create runs no sweep;
+ * art_batch_launch replays the graph on hip_stream (asynchronous);
+ * art_batch_stats synchronises with the last launch and returns the segment-
+ * bin updates it performed and its HIP-event time.  The meshes must not be
+ * re-tuned, re-filled with a different bin count or destroyed while the batch
+ * exists (their buffers are captured in the graph). */
+typedef struct art_batch art_batch;
+int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const float *const *gamma_w,
+                     float I_bc, const art_outputs *outs, int waves, art_batch **out,
+                     void *hip_stream);
+int art_batch_launch(art_batch *batch, void *hip_stream);
+int art_batch_stats(art_batch *batch, long long *segment_bins, float *ms);
+int art_batch_destroy(art_batch *batch);
 
 /* Number of directions of an Nside (12 nside^2), or ART_E_INVAL. */
 int art_ndirs(int nside);

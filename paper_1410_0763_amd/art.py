@@ -20,8 +20,9 @@ MAX_NSIDE = 64
 
 # Every symbol include/art.h declares.
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
-           "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning", "art_ndirs",
-           "art_last_error")
+           "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
+           "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
+           "art_ndirs", "art_last_error")
 
 
 class ArtError(RuntimeError):
@@ -36,8 +37,7 @@ class Outputs(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("bx", ctypes.c_int), ("by", ctypes.c_int), ("bz", ctypes.c_int),
-                ("subsets", ctypes.c_int), ("threads", ctypes.c_int)]
+    _fields_ = [("depth", ctypes.c_int), ("subsets", ctypes.c_int), ("waves", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -64,6 +64,11 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.art_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.art_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.art_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i), i, ctypes.POINTER(vp), f,
+                                   ctypes.POINTER(Outputs), i, ctypes.POINTER(vp), vp]
+    L.art_batch_launch.argtypes = [vp, vp]
+    L.art_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_float)]
+    L.art_batch_destroy.argtypes = [vp]
     L.art_ndirs.argtypes = [i]
     L.art_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -136,8 +141,8 @@ class Mesh:
         self.nbins = kappa.shape[0]
 
     # -- tuning ----------------------------------------------------------
-    def set_tuning(self, bx, by, bz, subsets, threads):
-        t = Tuning(bx, by, bz, subsets, threads)
+    def set_tuning(self, depth, subsets, waves):
+        t = Tuning(depth, subsets, waves)
         _check(load().art_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -189,3 +194,56 @@ class Mesh:
         _check(load().art_sweep_range(self._h, nside, d_begin, d_end, float(I_bc), _ptr(A1),
                                       _ptr(A2), _stream_ptr(stream)))
         return A1, A2
+
+
+class Batch:
+    """Several meshes swept by one graph-captured launch sequence (art_batch_*).
+
+    meshes: list of Mesh (fields set); nsides: list of int; gamma_ws: list of
+    per-mesh weight sequences or None.  Output tensors are allocated here and
+    kept alive as long as the batch (the graph writes into them)."""
+
+    def __init__(self, meshes, nsides, gamma_ws=None, I_bc: float = 0.0, waves: int = 8,
+                 stream=None):
+        L = load()
+        n = len(meshes)
+        self.meshes = list(meshes)
+        self.outs = [m.alloc_outputs(ns) for m, ns in zip(meshes, nsides)]
+        outs = (Outputs * n)(*[Outputs(*(_ptr(o.get(k)) for k in
+                                          ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
+                               for o in self.outs])
+        hs = (ctypes.c_void_p * n)(*[m._h for m in meshes])
+        ns_arr = (ctypes.c_int * n)(*[int(v) for v in nsides])
+        self._gw_keep = []
+        gw_arr = (ctypes.c_void_p * n)()
+        for idx in range(n):
+            g = None if gamma_ws is None else gamma_ws[idx]
+            if g is not None:
+                arr = (ctypes.c_float * len(g))(*[float(v) for v in g])
+                self._gw_keep.append(arr)
+                gw_arr[idx] = ctypes.cast(arr, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(L.art_batch_create(hs, ns_arr, n, gw_arr, float(I_bc), outs, int(waves),
+                                  ctypes.byref(h), _stream_ptr(stream)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().art_batch_launch(self._h, _stream_ptr(stream)))
+        return self.outs
+
+    def stats(self) -> dict:
+        seg = ctypes.c_longlong()
+        ms = ctypes.c_float()
+        _check(load().art_batch_stats(self._h, ctypes.byref(seg), ctypes.byref(ms)))
+        return dict(segment_bins=seg.value, ms=ms.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().art_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,8 @@
 // normalisation/rates -> optional exit sums.  Everything is queued on the
 // caller's stream; nothing in a sweep synchronises the host.
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -61,7 +63,7 @@ struct art_mesh {
     double h = 1.0;
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
-    art_tuning tune{16, 16, 8, 2, 512};
+    art_tuning tune{32, 1, 8};
 
     float4 *fields = nullptr; size_t fields_cap = 0;
     int *bad = nullptr; size_t bad_cap = 0;
@@ -79,6 +81,7 @@ struct art_mesh {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // start, march start, march end, end
     bool timed = false;
     std::vector<int> wave_off;          // [W + 1]
+    std::vector<ArtItem> items_host;    // the same items on the host
     int sched_key[6] = {0, 0, 0, 0, 0, 0};
     ArtMeshDesc *desc = nullptr; size_t desc_cap = 0;
     ArtMeshDesc desc_host{};
@@ -91,40 +94,49 @@ int nblocks(int n, int b) { return (n + b - 1) / b; }
 
 int validate_tuning(const art_tuning &t, int nb)
 {
-    if (t.bx < 1 || t.by < 1 || t.bz < 1 || t.bx > 128 || t.by > 128 || t.bz > 128)
-        return fail(ART_E_INVAL, "tuning: block sides must be in [1, 128]");
+    if (t.depth < 1 || t.depth > 256) return fail(ART_E_INVAL, "tuning: depth must be in [1, 256]");
     if (t.subsets < 1 || t.subsets > 64) return fail(ART_E_INVAL, "tuning: subsets must be in [1, 64]");
-    if (t.threads < 64 || t.threads > 1024 || t.threads % 64)
-        return fail(ART_E_INVAL, "tuning: threads must be a multiple of 64 in [64, 1024]");
-    const long long lds = (long long)art_march_lds_floats(t.bx, t.by, t.bz, std::max(nb, 1)) * 4;
+    if (t.waves < 1 || t.waves > 16) return fail(ART_E_INVAL, "tuning: waves must be in [1, 16]");
+    const long long lds = (long long)art_march_lds_floats(t.depth, std::max(nb, 1)) * 4;
     if (lds > art_march_max_lds_bytes())
         return fail(ART_E_UNSUPPORTED, "tuning: block accumulators need " + std::to_string(lds) +
                                            " bytes of LDS, above the workgroup limit");
     return ART_OK;
 }
 
-// Work items of the block wavefronts: launch w holds, for every octant o, the
-// blocks whose indices counted along o's travel directions sum to w, once per
-// direction subset.
+// Work items of the block wavefronts.  For dominant axis a the blocks are
+// 8 x 8 columns (axes b < c) by `depth` cells along a; launch w holds, for
+// every (a, octant) group, the blocks whose indices counted along the group's
+// travel directions sum to w, once per direction subset.
 int build_schedule(art_mesh *m)
 {
     const art_tuning &t = m->tune;
-    const int key[6] = {m->nx, m->ny, m->nz, t.bx * 1000000 + t.by * 1000 + t.bz, t.subsets, 1};
+    const int key[6] = {m->nx, m->ny, m->nz, t.depth, t.subsets, 2};
     if (m->items && std::equal(key, key + 6, m->sched_key)) return ART_OK;
-    const int nbx = nblocks(m->nx, t.bx), nby = nblocks(m->ny, t.by), nbz = nblocks(m->nz, t.bz);
-    const int W = nbx + nby + nbz - 2;
-    std::vector<std::vector<ArtItem>> waves(W);
-    for (int o = 0; o < 8; ++o)
-        for (int r = 0; r < nbz; ++r)
-            for (int q = 0; q < nby; ++q)
-                for (int p = 0; p < nbx; ++p) {
-                    const int pp = (o & 1) ? nbx - 1 - p : p;
-                    const int qq = (o & 2) ? nby - 1 - q : q;
-                    const int rr = (o & 4) ? nbz - 1 - r : r;
-                    const int blk = (r * nby + q) * nbx + p;
-                    for (int s = 0; s < t.subsets; ++s)
-                        waves[pp + qq + rr].push_back(ArtItem{0, blk, o * t.subsets + s, 0});
-                }
+    const int N[3] = {m->nx, m->ny, m->nz};
+    std::vector<std::vector<ArtItem>> waves;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        int nblk[3];
+        nblk[a] = nblocks(N[a], t.depth);
+        nblk[b] = nblocks(N[b], 8);
+        nblk[c] = nblocks(N[c], 8);
+        const int W = nblk[0] + nblk[1] + nblk[2] - 2;
+        if ((int)waves.size() < W) waves.resize(W);
+        for (int o = 0; o < 8; ++o)
+            for (int pa = 0; pa < nblk[a]; ++pa)
+                for (int pc = 0; pc < nblk[c]; ++pc)
+                    for (int pb = 0; pb < nblk[b]; ++pb) {
+                        int p[3];
+                        p[a] = pa; p[b] = pb; p[c] = pc;
+                        int wsum = 0;
+                        for (int ax = 0; ax < 3; ++ax)
+                            wsum += ((o >> ax) & 1) ? nblk[ax] - 1 - p[ax] : p[ax];
+                        const int blk = (pa * nblk[c] + pc) * nblk[b] + pb;
+                        for (int s = 0; s < t.subsets; ++s)
+                            waves[wsum].push_back(ArtItem{0, blk, (a * 8 + o) * t.subsets + s, 0});
+                    }
+    }
     std::vector<ArtItem> flat;
     m->wave_off.assign(1, 0);
     for (auto &w : waves) {
@@ -136,6 +148,7 @@ int build_schedule(art_mesh *m)
     if (rc) return rc;
     if ((rc = dev_alloc(&m->seg_count, flat.size(), &m->seg_cap))) return rc;
     HIPCHK(hipMemcpy(m->items, flat.data(), flat.size() * sizeof(ArtItem), hipMemcpyHostToDevice));
+    m->items_host = flat;
     std::copy(key, key + 6, m->sched_key);
     return ART_OK;
 }
@@ -156,7 +169,7 @@ long long state_bound(const art_mesh *m, int nd)
 int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
 {
     const int nd = 12 * nside * nside;
-    const int nbk = 8 * m->tune.subsets;
+    const int nbk = 24 * m->tune.subsets;
     int rc;
     if ((rc = dev_alloc(&m->dirs, (size_t)nd, &m->dirs_cap))) return rc;
     if ((rc = dev_alloc(&m->order, (size_t)nd, &m->order_cap))) return rc;
@@ -173,8 +186,8 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     d.bucket_start = m->bucket_start;
     d.ncell = m->ncell;
     d.nx = m->nx; d.ny = m->ny; d.nz = m->nz; d.nb = m->nb;
-    d.bx = m->tune.bx; d.by = m->tune.by; d.bz = m->tune.bz;
-    d.nbx = nblocks(m->nx, d.bx); d.nby = nblocks(m->ny, d.by); d.nbz = nblocks(m->nz, d.bz);
+    d.depth = m->tune.depth;
+    d.subsets = m->tune.subsets;
     d.I_bc = I_bc;
     d.nbuckets = nbk;
     if ((rc = dev_alloc(&m->desc, 1, &m->desc_cap))) return rc;
@@ -198,11 +211,11 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
     HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
                            m->dirs, m->order, m->bucket_start, st));
     HIPCHK(hipEventRecord(m->ev[1], st));
-    const int lds_floats = art_march_lds_floats(m->tune.bx, m->tune.by, m->tune.bz, m->nb);
+    const int lds_floats = art_march_lds_floats(m->tune.depth, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
         const int n = m->wave_off[w + 1] - m->wave_off[w];
         HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, lds_floats,
-                                m->tune.threads, m->seg_count + m->wave_off[w], st));
+                                64 * m->tune.waves, m->seg_count + m->wave_off[w], st));
     }
     HIPCHK(hipEventRecord(m->ev[2], st));
     return ART_OK;
@@ -215,6 +228,71 @@ int check_mesh_ready(const art_mesh *m, int nside)
     if (nside < 1 || nside > ART_MAX_NSIDE)
         return fail(ART_E_INVAL, "nside must be in [1, " + std::to_string(ART_MAX_NSIDE) + "]");
     return ART_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched form: several meshes (each with its own shape, Nside, bins and
+// tuning) marched by one launch sequence.  Launch (w, nb) holds the
+// wavefront-w items of every mesh with nb bins; items index a descriptor
+// array of all meshes.  The whole sequence is captured once into a hipGraph
+// on an internal stream and replayed on the caller's stream.
+// ---------------------------------------------------------------------------
+struct art_batch {
+    std::vector<art_mesh *> meshes;
+    std::vector<int> nside;
+    std::vector<art_outputs> outs;
+    std::vector<std::array<float, 4>> gw;
+    float I_bc = 0.0f;
+    int waves = 8;
+    ArtMeshDesc *descs = nullptr; size_t descs_cap = 0;
+    ArtItem *items = nullptr; size_t items_cap = 0;
+    unsigned int *seg_count = nullptr; size_t seg_cap = 0;
+    struct Launch { int off, n, nb, lds; };
+    std::vector<Launch> launches;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool launched = false;
+};
+
+namespace {
+
+int batch_enqueue(art_batch *B, hipStream_t st)
+{
+    const int n = (int)B->meshes.size();
+    for (int i = 0; i < n; ++i) {
+        art_mesh *m = B->meshes[i];
+        HIPCHK(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
+                               m->tune.subsets, m->dirs, m->order, m->bucket_start, st));
+    }
+    for (const auto &L : B->launches)
+        HIPCHK(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.lds, 64 * B->waves,
+                                B->seg_count + L.off, st));
+    for (int i = 0; i < n; ++i) {
+        art_mesh *m = B->meshes[i];
+        const art_outputs &o = B->outs[i];
+        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields, m->ncell,
+                                    m->nb, 12 * B->nside[i] * B->nside[i], B->gw[i].data(), o.J_in, o.J,
+                                    o.J_exact, o.Gamma, nullptr, nullptr, st));
+    }
+    return ART_OK;
+}
+
+void batch_free(art_batch *B)
+{
+    if (!B) return;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    for (hipEvent_t e : B->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (B->descs) (void)hipFree(B->descs);
+    if (B->items) (void)hipFree(B->items);
+    if (B->seg_count) (void)hipFree(B->seg_count);
+    delete B;
 }
 
 }  // namespace
@@ -322,7 +400,7 @@ int art_sweep(art_mesh *m, int nside, const float *gamma_w, float I_bc, const ar
         hipStream_t st = (hipStream_t)hip_stream;
         const int nd = 12 * nside * nside;
         if ((rc = run_sweep(m, nside, 0, nd, I_bc, st))) return rc;
-        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
+        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, gw, out->J_in, out->J, out->J_exact,
                                     out->Gamma, nullptr, nullptr, st));
         HIPCHK(hipEventRecord(m->ev[3], st));
@@ -353,7 +431,7 @@ int art_sweep_range(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, 
         hipStream_t st = (hipStream_t)hip_stream;
         if ((rc = run_sweep(m, nside, d_begin, d_end, I_bc, st))) return rc;
         const float ones[4] = {1.f, 1.f, 1.f, 1.f};
-        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 8 * m->tune.subsets, m->fields,
+        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, ones, nullptr, nullptr, nullptr, nullptr,
                                     A1, A2, st));
         HIPCHK(hipEventRecord(m->ev[3], st));
@@ -405,6 +483,130 @@ int art_get_tuning(const art_mesh *m, art_tuning *t)
 {
     if (!m || !t) return fail(ART_E_INVAL, "null argument");
     *t = m->tune;
+    return ART_OK;
+}
+
+
+int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const float *const *gamma_w,
+                     float I_bc, const art_outputs *outs, int waves, art_batch **out, void *hip_stream)
+{
+    art_batch *B = nullptr;
+    try {
+        if (!meshes || !nside || !outs || !out || n < 1)
+            return fail(ART_E_INVAL, "batch: null argument or n < 1");
+        if (waves < 1 || waves > 16) return fail(ART_E_INVAL, "batch: waves must be in [1, 16]");
+        if (!std::isfinite(I_bc)) return fail(ART_E_INVAL, "I_bc must be finite");
+        hipStream_t st = (hipStream_t)hip_stream;
+        B = new art_batch;
+        B->I_bc = I_bc;
+        B->waves = waves;
+        std::vector<ArtMeshDesc> descs;
+        // per (wavefront, nb): items of all meshes
+        std::map<std::pair<int, int>, std::vector<ArtItem>> groups;
+        std::map<std::pair<int, int>, int> lds;
+        for (int i = 0; i < n; ++i) {
+            art_mesh *m = meshes[i];
+            int rc = check_mesh_ready(m, nside[i]);
+            if (rc) { batch_free(B); return rc; }
+            for (int j = 0; j < i; ++j)
+                if (meshes[j] == m) { batch_free(B); return fail(ART_E_INVAL, "batch: a mesh appears twice"); }
+            if ((rc = prepare(m, nside[i], I_bc, st))) { batch_free(B); return rc; }
+            descs.push_back(m->desc_host);
+            B->meshes.push_back(m);
+            B->nside.push_back(nside[i]);
+            B->outs.push_back(outs[i]);
+            std::array<float, 4> g = {1.f, 1.f, 1.f, 1.f};
+            if (gamma_w && gamma_w[i])
+                for (int b = 0; b < m->nb; ++b) g[b] = gamma_w[i][b];
+            B->gw.push_back(g);
+            const int lf = art_march_lds_floats(m->tune.depth, m->nb);
+            for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
+                auto key = std::make_pair((int)w, m->nb);
+                auto &v = groups[key];
+                for (int q = m->wave_off[w]; q < m->wave_off[w + 1]; ++q) {
+                    ArtItem it = m->items_host[q];
+                    it.mesh = i;
+                    v.push_back(it);
+                }
+                lds[key] = std::max(lds[key], lf);
+            }
+        }
+        std::vector<ArtItem> flat;
+        for (auto &kv : groups) {
+            art_batch::Launch L{(int)flat.size(), (int)kv.second.size(), kv.first.second, lds[kv.first]};
+            flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+            B->launches.push_back(L);
+        }
+        int rc;
+        if ((rc = dev_alloc(&B->descs, descs.size(), &B->descs_cap))) { batch_free(B); return rc; }
+        if ((rc = dev_alloc(&B->items, flat.size(), &B->items_cap))) { batch_free(B); return rc; }
+        if ((rc = dev_alloc(&B->seg_count, flat.size(), &B->seg_cap))) { batch_free(B); return rc; }
+        hipError_t e = hipMemcpy(B->descs, descs.data(), descs.size() * sizeof(ArtMeshDesc), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(B->items, flat.data(), flat.size() * sizeof(ArtItem), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&B->ev[0]);
+        if (e == hipSuccess) e = hipEventCreate(&B->ev[1]);
+        if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("batch setup: ") + hipGetErrorString(e)); }
+        // the march kernels may need more LDS than the default: set it before capture
+        for (const auto &L : B->launches) {
+            e = art_launch_march(nullptr, 0, nullptr, L.nb, L.lds, 64 * waves, nullptr, B->cap);
+            if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, hipGetErrorString(e)); }
+        }
+        e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("capture: ") + hipGetErrorString(e)); }
+        rc = batch_enqueue(B, B->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(B->cap, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); batch_free(B); return rc; }
+        if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("capture end: ") + hipGetErrorString(e)); }
+        B->graph = g;
+        e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
+        *out = B;
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        batch_free(B);
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        batch_free(B);
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_batch_launch(art_batch *B, void *hip_stream)
+{
+    if (!B || !B->exec) return fail(ART_E_INVAL, "batch is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipEventRecord(B->ev[0], st));
+    HIPCHK(hipGraphLaunch(B->exec, st));
+    HIPCHK(hipEventRecord(B->ev[1], st));
+    B->launched = true;
+    g_err.clear();
+    return ART_OK;
+}
+
+int art_batch_stats(art_batch *B, long long *segment_bins, float *ms)
+{
+    if (!B) return fail(ART_E_INVAL, "batch is NULL");
+    if (!B->launched) return fail(ART_E_STATE, "batch has not been launched");
+    HIPCHK(hipEventSynchronize(B->ev[1]));
+    if (ms) HIPCHK(hipEventElapsedTime(ms, B->ev[0], B->ev[1]));
+    if (segment_bins) {
+        std::vector<unsigned int> h(B->seg_cap);
+        HIPCHK(hipMemcpy(h.data(), B->seg_count, h.size() * sizeof(unsigned int), hipMemcpyDeviceToHost));
+        long long tot = 0;
+        for (const auto &L : B->launches)
+            for (int q = L.off; q < L.off + L.n; ++q) tot += (long long)h[q] * L.nb;
+        *segment_bins = tot;
+    }
+    g_err.clear();
+    return ART_OK;
+}
+
+int art_batch_destroy(art_batch *B)
+{
+    batch_free(B);
     return ART_OK;
 }
 

@@ -11,7 +11,8 @@
 // (rays at the half-integer points of the upstream face of the dominant axis,
 // unit spacing; ties of the dominant axis go to the lowest axis index within
 // 1e-12; components below 1e-12 are zero), the octant of travel, the workgroup
-// bucket (octant x subset) and the offset of its rays in the state buffer.
+// bucket (dominant axis x octant x subset) and the offset of its rays in the
+// state buffer.
 //
 // One workgroup: every thread builds directions; wave 0 then assigns buckets
 // and offsets with wave-wide prefix sums, so the result is deterministic.
@@ -105,20 +106,22 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
     __syncthreads();
     if (threadIdx.x >= 64) return;
 
-    // Wave 0: rank of each in-range direction within its octant (ballot
-    // prefix counts in index order), bucket = octant * subsets + rank % subsets,
-    // and the state-buffer offsets (prefix sum of nj * nk * nb).
+    // Wave 0: rank of each in-range direction within its group g = a * 8 +
+    // octant (ballot prefix counts in index order), bucket = g * subsets +
+    // rank % subsets, and the state-buffer offsets (prefix sum of nj nk nb).
     const int lane = threadIdx.x;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int oct_count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int oct_count[24];
+#pragma unroll
+    for (int g = 0; g < 24; ++g) oct_count[g] = 0;
     long long off_base = 0;
     for (int base = 0; base < nd; base += 64) {
         const int d = base + lane;
         const bool valid = d < nd && d >= d_begin && d < d_end;
-        const int oct = (d < nd) ? dirs[d].octant : -1;
+        const int oct = (d < nd) ? dirs[d].a * 8 + dirs[d].octant : -1;
         int rank = 0;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
+        for (int o = 0; o < 24; ++o) {
             const unsigned long long msk = __ballot(valid && oct == o);
             if (valid && oct == o) rank = oct_count[o] + __popcll(msk & below);
             oct_count[o] += __popcll(msk);
@@ -144,11 +147,11 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
     };
     if (lane == 0) {
         int acc = 0;
-        for (int bk = 0; bk < 8 * subsets; ++bk) {
+        for (int bk = 0; bk < 24 * subsets; ++bk) {
             bucket_start[bk] = acc;
             acc += bucket_size(bk);
         }
-        bucket_start[8 * subsets] = acc;
+        bucket_start[24 * subsets] = acc;
     }
     for (int d = lane; d < nd; d += 64) {
         const int bk = dirs[d].bucket;   // written by this lane above

@@ -20,7 +20,7 @@ struct ArtDir {
     int octant;           // bit i set: the rays travel towards decreasing x_i
     int j0, nj, k0, nk;   // lattice index ranges [j0, j0+nj) x [k0, k0+nk)
     long long state_off;  // first float of this direction's ray states
-    int bucket;           // octant * subsets + subset; -1 outside the range
+    int bucket;           // (a * 8 + octant) * subsets + subset; -1 outside the range
     int pad;
 };
 
@@ -34,10 +34,10 @@ struct ArtMeshDesc {
     const int *bucket_start;   // [nbuckets + 1]
     long long ncell;
     int nx, ny, nz, nb;
-    int bx, by, bz;            // block shape
-    int nbx, nby, nbz;         // blocks per axis
+    int depth;                 // block cells along the dominant axis
+    int subsets;               // buckets per (dominant axis, octant) group
     float I_bc;
-    int nbuckets;
+    int nbuckets;              // 24 * subsets
 };
 
 // Work item of one wavefront launch: (mesh, block, bucket).
@@ -66,4 +66,4 @@ hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int n
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
 int art_march_max_lds_bytes();
-int art_march_lds_floats(int bx, int by, int bz, int nb);
+int art_march_lds_floats(int depth, int nb);
