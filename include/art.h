@@ -67,7 +67,8 @@ typedef struct {
 typedef struct {
     int depth;        /* cells of a block along the dominant axis, 1..256 */
     int subsets;      /* buckets per (dominant axis, octant) group, 1..64 */
-    int waves;        /* waves per workgroup, 1..16 */
+    int waves;        /* waves per workgroup, 1..8 */
+    int interleave;   /* directions marched together by one wave: 1, 2 or 4 */
 } art_tuning;
 
 /* Create a mesh of nx*ny*nz cubic cells of side cell_size (> 0).
@@ -122,7 +123,7 @@ int art_get_tuning(const art_mesh *mesh, art_tuning *t);
  * every mesh.  nside[i], gamma_w[i] (host array of the mesh's bins, or NULL),
  * outs[i] (caller-owned device buffers, which must outlive the batch) as in
  * art_sweep; exit sums are not produced (outs[i].exit_sum is ignored).  waves:
- * waves per workgroup for all meshes, 1..16.  art_batch_create runs no sweep;
+ * waves per workgroup for all meshes, 1..8.  art_batch_create runs no sweep;
  * art_batch_launch replays the graph on hip_stream (asynchronous);
  * art_batch_stats synchronises with the last launch and returns the segment-
  * bin updates it performed and its HIP-event time.  The meshes must not be

@@ -37,7 +37,8 @@ class Outputs(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("depth", ctypes.c_int), ("subsets", ctypes.c_int), ("waves", ctypes.c_int)]
+    _fields_ = [("depth", ctypes.c_int), ("subsets", ctypes.c_int), ("waves", ctypes.c_int),
+                ("interleave", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -141,8 +142,8 @@ class Mesh:
         self.nbins = kappa.shape[0]
 
     # -- tuning ----------------------------------------------------------
-    def set_tuning(self, depth, subsets, waves):
-        t = Tuning(depth, subsets, waves)
+    def set_tuning(self, depth, subsets, waves, interleave=2):
+        t = Tuning(depth, subsets, waves, interleave)
         _check(load().art_set_tuning(self._h, ctypes.byref(t)))
 
     def get_tuning(self) -> dict:

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -63,7 +64,7 @@ struct art_mesh {
     double h = 1.0;
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
-    art_tuning tune{32, 1, 8};
+    art_tuning tune{32, 1, 8, 4};
 
     float4 *fields = nullptr; size_t fields_cap = 0;
     int *bad = nullptr; size_t bad_cap = 0;
@@ -73,6 +74,7 @@ struct art_mesh {
     int *order = nullptr; size_t order_cap = 0;
     int *bucket_start = nullptr; size_t bs_cap = 0;
     float *state = nullptr; size_t state_cap = 0;
+    float4 *geo = nullptr; size_t geo_cap = 0;
     float *acc = nullptr; size_t acc_cap = 0;
 
     // schedule (depends on shape and tuning only)
@@ -96,7 +98,9 @@ int validate_tuning(const art_tuning &t, int nb)
 {
     if (t.depth < 1 || t.depth > 256) return fail(ART_E_INVAL, "tuning: depth must be in [1, 256]");
     if (t.subsets < 1 || t.subsets > 64) return fail(ART_E_INVAL, "tuning: subsets must be in [1, 64]");
-    if (t.waves < 1 || t.waves > 16) return fail(ART_E_INVAL, "tuning: waves must be in [1, 16]");
+    if (t.waves < 1 || t.waves > 8) return fail(ART_E_INVAL, "tuning: waves must be in [1, 8]");
+    if (t.interleave != 1 && t.interleave != 2 && t.interleave != 4)
+        return fail(ART_E_INVAL, "tuning: interleave must be 1, 2 or 4");
     const long long lds = (long long)art_march_lds_floats(t.depth, std::max(nb, 1)) * 4;
     if (lds > art_march_max_lds_bytes())
         return fail(ART_E_UNSUPPORTED, "tuning: block accumulators need " + std::to_string(lds) +
@@ -175,6 +179,8 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     if ((rc = dev_alloc(&m->order, (size_t)nd, &m->order_cap))) return rc;
     if ((rc = dev_alloc(&m->bucket_start, (size_t)nbk + 1, &m->bs_cap))) return rc;
     if ((rc = dev_alloc(&m->state, (size_t)state_bound(m, nd), &m->state_cap))) return rc;
+    const int gstride = std::max(m->nx, std::max(m->ny, m->nz));
+    if ((rc = dev_alloc(&m->geo, (size_t)nd * gstride, &m->geo_cap))) return rc;
     if ((rc = dev_alloc(&m->acc, (size_t)nbk * m->nb * 2 * m->ncell, &m->acc_cap))) return rc;
     if ((rc = build_schedule(m))) return rc;
     ArtMeshDesc d{};
@@ -184,6 +190,9 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     d.dirs = m->dirs;
     d.order = m->order;
     d.bucket_start = m->bucket_start;
+    d.geo = m->geo;
+    d.geo_stride = gstride;
+    d.interleave = m->tune.interleave;
     d.ncell = m->ncell;
     d.nx = m->nx; d.ny = m->ny; d.nz = m->nz; d.nb = m->nb;
     d.depth = m->tune.depth;
@@ -201,21 +210,23 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     return ART_OK;
 }
 
-int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStream_t st)
+int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStream_t st,
+              bool fill_state = false)
 {
     int rc = prepare(m, nside, I_bc, st);
     if (rc) return rc;
+    if (fill_state) HIPCHK(art_launch_fill(m->state, (long long)m->state_cap, I_bc, st));
     if (!m->ev[0])
         for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&m->ev[i]));
     HIPCHK(hipEventRecord(m->ev[0], st));
     HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
-                           m->dirs, m->order, m->bucket_start, st));
+                           m->dirs, m->order, m->bucket_start, m->geo, m->desc_host.geo_stride, st));
     HIPCHK(hipEventRecord(m->ev[1], st));
     const int lds_floats = art_march_lds_floats(m->tune.depth, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
         const int n = m->wave_off[w + 1] - m->wave_off[w];
-        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, lds_floats,
-                                64 * m->tune.waves, m->seg_count + m->wave_off[w], st));
+        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, m->tune.interleave,
+                                lds_floats, 64 * m->tune.waves, m->seg_count + m->wave_off[w], st));
     }
     HIPCHK(hipEventRecord(m->ev[2], st));
     return ART_OK;
@@ -249,7 +260,7 @@ struct art_batch {
     ArtMeshDesc *descs = nullptr; size_t descs_cap = 0;
     ArtItem *items = nullptr; size_t items_cap = 0;
     unsigned int *seg_count = nullptr; size_t seg_cap = 0;
-    struct Launch { int off, n, nb, lds; };
+    struct Launch { int off, n, nb, lds, interleave; };
     std::vector<Launch> launches;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -266,11 +277,12 @@ int batch_enqueue(art_batch *B, hipStream_t st)
     for (int i = 0; i < n; ++i) {
         art_mesh *m = B->meshes[i];
         HIPCHK(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
-                               m->tune.subsets, m->dirs, m->order, m->bucket_start, st));
+                               m->tune.subsets, m->dirs, m->order, m->bucket_start, m->geo,
+                               m->desc_host.geo_stride, st));
     }
     for (const auto &L : B->launches)
-        HIPCHK(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.lds, 64 * B->waves,
-                                B->seg_count + L.off, st));
+        HIPCHK(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,
+                                64 * B->waves, B->seg_count + L.off, st));
     for (int i = 0; i < n; ++i) {
         art_mesh *m = B->meshes[i];
         const art_outputs &o = B->outs[i];
@@ -333,7 +345,7 @@ int art_destroy_mesh(art_mesh *m)
 {
     if (!m) return ART_OK;
     void *bufs[] = {m->fields, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
-                    m->state, m->acc, m->items, m->desc, m->seg_count};
+                    m->state, m->geo, m->acc, m->items, m->desc, m->seg_count};
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
     for (void *p : bufs)
@@ -399,7 +411,7 @@ int art_sweep(art_mesh *m, int nside, const float *gamma_w, float I_bc, const ar
             }
         hipStream_t st = (hipStream_t)hip_stream;
         const int nd = 12 * nside * nside;
-        if ((rc = run_sweep(m, nside, 0, nd, I_bc, st))) return rc;
+        if ((rc = run_sweep(m, nside, 0, nd, I_bc, st, out->exit_sum != nullptr))) return rc;
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, gw, out->J_in, out->J, out->J_exact,
                                     out->Gamma, nullptr, nullptr, st));
@@ -494,7 +506,7 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
     try {
         if (!meshes || !nside || !outs || !out || n < 1)
             return fail(ART_E_INVAL, "batch: null argument or n < 1");
-        if (waves < 1 || waves > 16) return fail(ART_E_INVAL, "batch: waves must be in [1, 16]");
+        if (waves < 1 || waves > 8) return fail(ART_E_INVAL, "batch: waves must be in [1, 8]");
         if (!std::isfinite(I_bc)) return fail(ART_E_INVAL, "I_bc must be finite");
         hipStream_t st = (hipStream_t)hip_stream;
         B = new art_batch;
@@ -502,8 +514,8 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         B->waves = waves;
         std::vector<ArtMeshDesc> descs;
         // per (wavefront, nb): items of all meshes
-        std::map<std::pair<int, int>, std::vector<ArtItem>> groups;
-        std::map<std::pair<int, int>, int> lds;
+        std::map<std::tuple<int, int, int>, std::vector<ArtItem>> groups;
+        std::map<std::tuple<int, int, int>, int> lds;
         for (int i = 0; i < n; ++i) {
             art_mesh *m = meshes[i];
             int rc = check_mesh_ready(m, nside[i]);
@@ -521,7 +533,7 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
             B->gw.push_back(g);
             const int lf = art_march_lds_floats(m->tune.depth, m->nb);
             for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
-                auto key = std::make_pair((int)w, m->nb);
+                auto key = std::make_tuple((int)w, m->nb, m->tune.interleave);
                 auto &v = groups[key];
                 for (int q = m->wave_off[w]; q < m->wave_off[w + 1]; ++q) {
                     ArtItem it = m->items_host[q];
@@ -533,7 +545,8 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         }
         std::vector<ArtItem> flat;
         for (auto &kv : groups) {
-            art_batch::Launch L{(int)flat.size(), (int)kv.second.size(), kv.first.second, lds[kv.first]};
+            art_batch::Launch L{(int)flat.size(), (int)kv.second.size(), std::get<1>(kv.first),
+                                lds[kv.first], std::get<2>(kv.first)};
             flat.insert(flat.end(), kv.second.begin(), kv.second.end());
             B->launches.push_back(L);
         }
@@ -549,7 +562,7 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("batch setup: ") + hipGetErrorString(e)); }
         // the march kernels may need more LDS than the default: set it before capture
         for (const auto &L : B->launches) {
-            e = art_launch_march(nullptr, 0, nullptr, L.nb, L.lds, 64 * waves, nullptr, B->cap);
+            e = art_launch_march(nullptr, 0, nullptr, L.nb, L.interleave, L.lds, 64 * waves, nullptr, B->cap);
             if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, hipGetErrorString(e)); }
         }
         e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);

@@ -162,13 +162,46 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
     }
 }
 
+
+// Per-(direction, slab) crossing table used by the march: for slab i of the
+// depth axis, the transverse lattice shift B(i) = floor(1/2 + t i) of every
+// ray changes by sh = B(i+1) - B(i) in {-1, 0, 1} at depth fraction
+// f = (X - (1/2 + t i)) / t (X the plane crossed), per transverse axis.
+// Entry: {f_b, f_c, sh_b, sh_c} (f = 2 when there is no crossing).
+__global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__ dirs, int nx, int ny,
+                                                      int nz, int stride, float4 *__restrict__ geo)
+{
+    const int d = blockIdx.x;
+    const ArtDir &D = dirs[d];
+    if (D.bucket < 0) return;
+    const int N[3] = {nx, ny, nz};
+    const int Na = N[D.a];
+    const double tb = D.beta[D.b], tc = D.beta[D.c];
+    const double rtb = D.rbeta[D.b], rtc = D.rbeta[D.c];
+    for (int i = threadIdx.x; i < Na; i += blockDim.x) {
+        const double xb0 = fma(tb, (double)i, 0.5), xb1 = fma(tb, (double)(i + 1), 0.5);
+        const double xc0 = fma(tc, (double)i, 0.5), xc1 = fma(tc, (double)(i + 1), 0.5);
+        const int Bb = (int)floor(xb0), Bc = (int)floor(xc0);
+        const int shb = max(-1, min(1, (int)floor(xb1) - Bb));
+        const int shc = max(-1, min(1, (int)floor(xc1) - Bc));
+        double fb = 2.0, fc = 2.0;
+        if (shb) fb = fmin(1.0, fmax(0.0, ((double)(shb > 0 ? Bb + 1 : Bb) - xb0) * rtb));
+        if (shc) fc = fmin(1.0, fmax(0.0, ((double)(shc > 0 ? Bc + 1 : Bc) - xc0) * rtc));
+        geo[(long long)d * stride + i] = make_float4((float)fb, (float)fc, (float)shb, (float)shc);
+    }
+}
+
 }  // namespace
 
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
-                           int subsets, ArtDir *dirs, int *order, int *bucket_start,
-                           hipStream_t stream)
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start, float4 *geo,
+                           int geo_stride, hipStream_t stream)
 {
     hipLaunchKernelGGL(art_dirs_kernel, dim3(1), dim3(256), 0, stream, nside, nx, ny, nz, nb,
                        d_begin, d_end, subsets, dirs, order, bucket_start);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(art_geo_kernel, dim3(12 * nside * nside), dim3(256), 0, stream, dirs, nx, ny,
+                       nz, geo_stride, geo);
     return hipGetLastError();
 }

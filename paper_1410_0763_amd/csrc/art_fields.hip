@@ -12,7 +12,11 @@
 //
 // Exit sums: after a sweep every ray's state slot holds the intensity with
 // which it left the mesh; one workgroup per direction adds up I_exit - I_bc
-// over the rays that cross the mesh (photon-balance diagnostics).
+// over the rays that cross the mesh (photon-balance diagnostics).  Rays that
+// only touch the mesh (chords of rounding size) are never marched; the state
+// buffer is filled with I_bc before such a sweep so that they add nothing.
+#include <algorithm>
+
 #include "art_internal.h"
 
 namespace {
@@ -32,6 +36,13 @@ __global__ __launch_bounds__(256) void art_layout_kernel(const float *__restrict
         const float kh = k * h;
         fields[c * nb + b] = make_float4(kh, kh > 0.0f ? 1.0f / kh : INFINITY, s, 0.0f);
     }
+}
+
+__global__ __launch_bounds__(256) void art_fill_kernel(float *__restrict__ p, long long n, float v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 struct GW {
@@ -117,6 +128,14 @@ hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell
     const long long nblk = (ncell + 255) / 256;
     hipLaunchKernelGGL(art_layout_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, kappa, S,
                        ncell, nb, (float)h, fields, bad_flag);
+    return hipGetLastError();
+}
+
+hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(art_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
     return hipGetLastError();
 }
 

@@ -32,7 +32,10 @@ struct ArtMeshDesc {
     const ArtDir *dirs;        // [N_d]
     const int *order;          // direction indices grouped by bucket
     const int *bucket_start;   // [nbuckets + 1]
+    const float4 *geo;         // [N_d][geo_stride] slab crossing table
     long long ncell;
+    int geo_stride;            // max(nx, ny, nz)
+    int interleave;            // directions marched together by one wave (1, 2, 4)
     int nx, ny, nz, nb;
     int depth;                 // block cells along the dominant axis
     int subsets;               // buckets per (dominant axis, octant) group
@@ -52,10 +55,10 @@ struct ArtItem {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
-                           int subsets, ArtDir *dirs, int *order, int *bucket_start,
-                           hipStream_t stream);
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start, float4 *geo,
+                           int geo_stride, hipStream_t stream);
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
-                            int lds_floats, int threads, unsigned int *seg_count,
+                            int interleave, int lds_floats, int threads, unsigned int *seg_count,
                             hipStream_t stream);
 hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
                              double h, float4 *fields, int *bad_flag, hipStream_t stream);
@@ -65,5 +68,6 @@ hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int n
                                 float *Gamma, float *A1raw, float *A2raw, hipStream_t stream);
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
+hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream);
 int art_march_max_lds_bytes();
 int art_march_lds_floats(int depth, int nb);

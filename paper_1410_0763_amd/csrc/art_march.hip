@@ -90,8 +90,25 @@ __device__ __forceinline__ void segment(const v4f *F, float ds, float invw, floa
     }
 }
 
-template <int NB>
-__global__ __launch_bounds__(1024) void art_march_kernel(const ArtItem *__restrict__ items,
+// Lane shift along b by one column (within each row of 8): row_shr:1 /
+// row_shl:1 of DPP move a value from the lane before / after; the lanes of
+// column 0 / 7, whose value comes from outside the row, are overwritten by
+// the caller.
+__device__ __forceinline__ float shift_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float shift_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+}
+
+typedef __attribute__((address_space(4))) const v4f c_f4;
+typedef __attribute__((address_space(4))) const ArtDir c_dir;
+typedef __attribute__((address_space(4))) const int c_int;
+
+template <int NB, int K>
+__global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restrict__ items,
                                                          const ArtMeshDesc *__restrict__ meshes,
                                                          unsigned int *__restrict__ seg_count)
 {
@@ -137,54 +154,56 @@ __global__ __launch_bounds__(1024) void art_march_kernel(const ArtItem *__restri
 
     g_f4 *fields = (g_f4 *)M.fields;
     g_f *state = (g_f *)M.state;
+    c_f4 *geo = (c_f4 *)M.geo;
+    c_dir *dirs = (c_dir *)M.dirs;
+    c_int *order = (c_int *)M.order;
+    const int gstride = M.geo_stride;
     const float I_bc = M.I_bc;
+    const long long xa0 = sig_neg ? Na - 1 - d0 : d0;
+    const long long cell0 = xa0 * sa + gb * sb + gc * sc;
+    const long long dcell = sig_neg ? -sa : sa;
     unsigned int nseg = 0;
 
-    for (int q = dbeg + wave; q < dend; q += nwave) {
-        const ArtDir &D = M.dirs[M.order[q]];
-        const double tb = D.beta[ab], tc = D.beta[ac];
-        const double rtb = D.rbeta[ab], rtc = D.rbeta[ac];
-        const float invw = (float)D.invw, wdir = (float)D.w;
-        const long long soff = D.state_off;
-        const int j0 = D.j0, nj = D.nj, k0 = D.k0;
-        // state slot of the ray in this lane's column when the shifts are (Bb, Bc)
-        auto slot = [&](int Bb_, int Bc_) -> long long {
-            return soff + ((long long)(gc - Bc_ - k0) * nj + (gb - Bb_ - j0)) * NB;
-        };
-
-        int Bb = (int)floor(fma(tb, (double)d0, 0.5));
-        int Bc = (int)floor(fma(tc, (double)d0, 0.5));
-        float I[NB];
+    // A wave marches K directions of the bucket together: q0 + m * nwave, m < K.
+    for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
+        bool act[K];
+        int dix[K], Bb[K], Bc[K], j0[K], nj[K], k0[K];
+        long long soff[K];
+        float invw[K], wdir[K];
+        float I[K][NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) I[b] = I_bc;
-        if (in_dom && d0 > 0) {
-            const long long sl = slot(Bb, Bc);
+        for (int m = 0; m < K; ++m) {
+            const int q = q0 + m * nwave;
+            act[m] = q < dend;
+            dix[m] = act[m] ? order[q] : order[q0];
+            const c_dir &D = dirs[dix[m]];
+            const double tb = ab == 0 ? D.beta[0] : D.beta[1];
+            const double tc = ac == 1 ? D.beta[1] : D.beta[2];
+            Bb[m] = (int)floor(fma(tb, (double)d0, 0.5));
+            Bc[m] = (int)floor(fma(tc, (double)d0, 0.5));
+            j0[m] = D.j0; nj[m] = D.nj; k0[m] = D.k0;
+            soff[m] = D.state_off;
+            invw[m] = (float)D.invw;
+            wdir[m] = (float)D.w;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) I[b] = state[sl + b];
+            for (int b = 0; b < NB; ++b) I[m][b] = I_bc;
+            if (act[m] && in_dom && d0 > 0) {
+                const long long sl = soff[m] + ((long long)(gc - Bc[m] - k0[m]) * nj[m] + (gb - Bb[m] - j0[m])) * NB;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) I[m][b] = state[sl + b];
+            }
         }
-        const int xa0 = sig_neg ? Na - 1 - d0 : d0;
-        long long cell = xa0 * sa + gb * sb + gc * sc;
-        const long long dcell = sig_neg ? -sa : sa;
         v4f F[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) F[b] = v4f{0.f, 0.f, 0.f, 0.f};
         if (in_dom) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) F[b] = fields[cell * NB + b];
+            for (int b = 0; b < NB; ++b) F[b] = fields[cell0 * NB + b];
         }
+        long long cell = cell0;
 
         for (int t = 0; t < nslab; ++t) {
             const int i = d0 + t;
-            // slab geometry, identical in every lane
-            const double xb0 = fma(tb, (double)i, 0.5), xb1 = fma(tb, (double)(i + 1), 0.5);
-            const double xc0 = fma(tc, (double)i, 0.5), xc1 = fma(tc, (double)(i + 1), 0.5);
-            const int shb = max(-1, min(1, (int)floor(xb1) - Bb));
-            const int shc = max(-1, min(1, (int)floor(xc1) - Bc));
-            double fb = 2.0, fc = 2.0;
-            if (shb) fb = fmin(1.0, fmax(0.0, ((double)(shb > 0 ? Bb + 1 : Bb) - xb0) * rtb));
-            if (shc) fc = fmin(1.0, fmax(0.0, ((double)(shc > 0 ? Bc + 1 : Bc) - xc0) * rtc));
-            const bool b_first = fb <= fc;
-
             // prefetch the next slab's fields
             v4f Fn[NB];
 #pragma unroll
@@ -193,84 +212,92 @@ __global__ __launch_bounds__(1024) void art_march_kernel(const ArtItem *__restri
 #pragma unroll
                 for (int b = 0; b < NB; ++b) Fn[b] = fields[(cell + dcell) * NB + b];
             }
-
-            // Rays arriving from outside this tile at the crossings: their
-            // states are loaded now, well before they are needed.
-            const int srcb = col - shb, srcc = row - shc;       // tile column the new ray comes from
-            const bool b_mesh = gb - shb >= 0 && gb - shb < Nb;  // source column inside the mesh
-            const bool c_mesh = gc - shc >= 0 && gc - shc < Nc;
-            const bool b_tile = srcb >= 0 && srcb <= 7;
-            const bool c_tile = srcc >= 0 && srcc <= 7;
-            float inb[NB], inc[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) inb[b] = inc[b] = I_bc;
-            if (shb && in_dom && b_mesh && !b_tile) {
-                const long long sl = slot(Bb + shb, b_first ? Bc : Bc + shc);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) inb[b] = state[sl + b];
-            }
-            if (shc && in_dom && c_mesh && !c_tile) {
-                const long long sl = slot(b_first ? Bb + shb : Bb, Bc + shc);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) inc[b] = state[sl + b];
-            }
-
             float a1[NB], a2[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) a1[b] = a2[b] = 0.0f;
+            unsigned int ns = 0;
 
-            // crossing of a b-plane: every ray moves from column gb to gb + shb
-            auto cross_b = [&]() {
-                const bool leaves = col + shb < 0 || col + shb > 7 || gb + shb < 0 || gb + shb >= Nb;
-                if (in_dom && leaves) {
-                    const long long sl = slot(Bb, Bc);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) state[sl + b] = I[b];
-                }
-                const int src = (row << 3) + min(7, max(0, srcb));
-                const bool take = b_tile && b_mesh;
+            for (int m = 0; m < K; ++m) {
+                if (!act[m]) continue;
+                const v4f g = geo[(long long)dix[m] * gstride + i];   // wave-uniform
+                const int shb = (int)g.z, shc = (int)g.w;
+                const float fb = g.x, fc = g.y;
+                const bool b_first = fb <= fc;
+                auto slot = [&](int Bb_, int Bc_) -> long long {
+                    return soff[m] + ((long long)(gc - Bc_ - k0[m]) * nj[m] + (gb - Bb_ - j0[m])) * NB;
+                };
+                // Rays arriving from outside this tile at the crossings.
+                const int srcb = col - shb, srcc = row - shc;
+                const bool b_mesh = gb - shb >= 0 && gb - shb < Nb;
+                const bool c_mesh = gc - shc >= 0 && gc - shc < Nc;
+                const bool b_tile = srcb >= 0 && srcb <= 7;
+                const bool c_tile = srcc >= 0 && srcc <= 7;
+                float inb[NB], inc[NB];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const float moved = lane_get(I[b], src);
-                    I[b] = take ? moved : inb[b];
-                }
-                Bb += shb;
-            };
-            auto cross_c = [&]() {
-                const bool leaves = row + shc < 0 || row + shc > 7 || gc + shc < 0 || gc + shc >= Nc;
-                if (in_dom && leaves) {
-                    const long long sl = slot(Bb, Bc);
+                for (int b = 0; b < NB; ++b) inb[b] = inc[b] = I_bc;
+                if (shb && in_dom && b_mesh && !b_tile) {
+                    const long long sl = slot(Bb[m] + shb, b_first ? Bc[m] : Bc[m] + shc);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) state[sl + b] = I[b];
+                    for (int b = 0; b < NB; ++b) inb[b] = state[sl + b];
                 }
-                const int src = (min(7, max(0, srcc)) << 3) + col;
-                const bool take = c_tile && c_mesh;
+                if (shc && in_dom && c_mesh && !c_tile) {
+                    const long long sl = slot(b_first ? Bb[m] + shb : Bb[m], Bc[m] + shc);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const float moved = lane_get(I[b], src);
-                    I[b] = take ? moved : inc[b];
+                    for (int b = 0; b < NB; ++b) inc[b] = state[sl + b];
                 }
-                Bc += shc;
-            };
-
-            unsigned int ns;
-            if (shb && shc) {
-                const float f1 = (float)fmin(fb, fc), f2 = (float)fmax(fb, fc);
-                segment<NB>(F, f1, invw, wdir, I, a1, a2);
-                if (b_first) cross_b(); else cross_c();
-                segment<NB>(F, f2 - f1, invw, wdir, I, a1, a2);
-                if (b_first) cross_c(); else cross_b();
-                segment<NB>(F, 1.0f - f2, invw, wdir, I, a1, a2);
-                ns = (f1 > 0.f) + (f2 - f1 > 0.f) + (1.0f - f2 > 0.f);
-            } else if (shb || shc) {
-                const float f1 = (float)(shb ? fb : fc);
-                segment<NB>(F, f1, invw, wdir, I, a1, a2);
-                if (shb) cross_b(); else cross_c();
-                segment<NB>(F, 1.0f - f1, invw, wdir, I, a1, a2);
-                ns = (f1 > 0.f) + (1.0f - f1 > 0.f);
-            } else {
-                segment<NB>(F, 1.0f, invw, wdir, I, a1, a2);
-                ns = 1;
+                float *Im = I[m];
+                // crossing of a b-plane: every ray moves from column gb to gb + shb
+                auto cross_b = [&]() {
+                    const bool leaves = col + shb < 0 || col + shb > 7 || gb + shb < 0 || gb + shb >= Nb;
+                    if (in_dom && leaves) {
+                        const long long sl = slot(Bb[m], Bc[m]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) state[sl + b] = Im[b];
+                    }
+                    const bool take = b_tile && b_mesh;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float moved = shb > 0 ? shift_prev(Im[b]) : shift_next(Im[b]);
+                        Im[b] = take ? moved : inb[b];
+                    }
+                    Bb[m] += shb;
+                };
+                // crossing of a c-plane: every ray moves from row gc to gc + shc
+                auto cross_c = [&]() {
+                    const bool leaves = row + shc < 0 || row + shc > 7 || gc + shc < 0 || gc + shc >= Nc;
+                    if (in_dom && leaves) {
+                        const long long sl = slot(Bb[m], Bc[m]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) state[sl + b] = Im[b];
+                    }
+                    const int src = (min(7, max(0, srcc)) << 3) + col;
+                    const bool take = c_tile && c_mesh;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float moved = lane_get(Im[b], src);
+                        Im[b] = take ? moved : inc[b];
+                    }
+                    Bc[m] += shc;
+                };
+                if (shb && shc) {
+                    const float f1 = fminf(fb, fc), f2 = fmaxf(fb, fc);
+                    segment<NB>(F, f1, invw[m], wdir[m], Im, a1, a2);
+                    if (b_first) cross_b(); else cross_c();
+                    segment<NB>(F, f2 - f1, invw[m], wdir[m], Im, a1, a2);
+                    if (b_first) cross_c(); else cross_b();
+                    segment<NB>(F, 1.0f - f2, invw[m], wdir[m], Im, a1, a2);
+                    ns += (f1 > 0.f) + (f2 - f1 > 0.f) + (1.0f - f2 > 0.f);
+                } else if (shb || shc) {
+                    const float f1 = shb ? fb : fc;
+                    segment<NB>(F, f1, invw[m], wdir[m], Im, a1, a2);
+                    if (shb) cross_b(); else cross_c();
+                    segment<NB>(F, 1.0f - f1, invw[m], wdir[m], Im, a1, a2);
+                    ns += (f1 > 0.f) + (1.0f - f1 > 0.f);
+                } else {
+                    segment<NB>(F, 1.0f, invw[m], wdir[m], Im, a1, a2);
+                    ns += 1;
+                }
             }
             if (in_dom) {
                 nseg += ns;
@@ -287,10 +314,13 @@ __global__ __launch_bounds__(1024) void art_march_kernel(const ArtItem *__restri
             for (int b = 0; b < NB; ++b) F[b] = Fn[b];
         }
         // rays leave through the block's far face (into the next block or out of the mesh)
-        if (in_dom) {
-            const long long sl = slot(Bb, Bc);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) state[sl + b] = I[b];
+        for (int m = 0; m < K; ++m) {
+            if (act[m] && in_dom) {
+                const long long sl = soff[m] + ((long long)(gc - Bc[m] - k0[m]) * nj[m] + (gb - Bb[m] - j0[m])) * NB;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) state[sl + b] = I[m][b];
+            }
         }
     }
 
@@ -322,28 +352,46 @@ int art_march_max_lds_bytes() { return 160 * 1024; }
 // LDS floats of one workgroup: accumulators of depth * 64 cells plus a counter.
 int art_march_lds_floats(int depth, int nb) { return nb * 2 * depth * 64 + 32; }
 
+
+template <int NB, int K>
+hipError_t launch_nbk(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, size_t bytes,
+                      int threads, unsigned int *seg_count, hipStream_t stream)
+{
+    static size_t configured = 64 * 1024;   // up to 64 KiB needs no opt-in
+    if (bytes > configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)art_march_kernel<NB, K>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        configured = bytes;
+    }
+    if (nitems <= 0) return hipSuccess;   // a call without items only configures the kernel
+    hipLaunchKernelGGL((art_march_kernel<NB, K>), dim3(nitems), dim3(threads), bytes, stream, items,
+                       meshes, seg_count);
+    return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_nb(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int K, size_t bytes,
+                     int threads, unsigned int *seg_count, hipStream_t stream)
+{
+    switch (K) {
+    case 1: return launch_nbk<NB, 1>(items, nitems, meshes, bytes, threads, seg_count, stream);
+    case 2: return launch_nbk<NB, 2>(items, nitems, meshes, bytes, threads, seg_count, stream);
+    case 4: return launch_nbk<NB, 4>(items, nitems, meshes, bytes, threads, seg_count, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
-                            int lds_floats, int threads, unsigned int *seg_count,
+                            int interleave, int lds_floats, int threads, unsigned int *seg_count,
                             hipStream_t stream)
 {
     const size_t bytes = (size_t)lds_floats * sizeof(float);
-    static size_t configured[5] = {0, 64 * 1024, 64 * 1024, 64 * 1024, 64 * 1024};
-    if (nb < 1 || nb > 4) return hipErrorInvalidValue;
-    const void *fn = nb == 1 ? (const void *)art_march_kernel<1>
-                   : nb == 2 ? (const void *)art_march_kernel<2>
-                   : nb == 3 ? (const void *)art_march_kernel<3>
-                             : (const void *)art_march_kernel<4>;
-    if (bytes > configured[nb]) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        configured[nb] = bytes;
-    }
-    if (nitems <= 0) return hipSuccess;   // a call without items only configures the kernel
     switch (nb) {
-    case 1: hipLaunchKernelGGL(art_march_kernel<1>, dim3(nitems), dim3(threads), bytes, stream, items, meshes, seg_count); break;
-    case 2: hipLaunchKernelGGL(art_march_kernel<2>, dim3(nitems), dim3(threads), bytes, stream, items, meshes, seg_count); break;
-    case 3: hipLaunchKernelGGL(art_march_kernel<3>, dim3(nitems), dim3(threads), bytes, stream, items, meshes, seg_count); break;
-    default: hipLaunchKernelGGL(art_march_kernel<4>, dim3(nitems), dim3(threads), bytes, stream, items, meshes, seg_count); break;
+    case 1: return launch_nb<1>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
+    case 2: return launch_nb<2>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
+    case 3: return launch_nb<3>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
+    case 4: return launch_nb<4>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }

@@ -42,12 +42,13 @@ def test_host_only_calls():
     t = art.Tuning()
     assert L.art_get_tuning(h, ctypes.byref(t)) == 0
     assert t.depth > 0 and t.subsets > 0 and t.waves > 0
-    for bad in (art.Tuning(32, 1, 0), art.Tuning(0, 1, 8), art.Tuning(300, 1, 8),
-                art.Tuning(32, 65, 8), art.Tuning(32, 1, 17)):
+    for bad in (art.Tuning(32, 1, 0, 2), art.Tuning(0, 1, 8, 2), art.Tuning(300, 1, 8, 2),
+                art.Tuning(32, 65, 8, 2), art.Tuning(32, 1, 9, 2), art.Tuning(32, 1, 8, 3)):
         assert L.art_set_tuning(h, ctypes.byref(bad)) == -1
-    ok = art.Tuning(16, 2, 4)
+    ok = art.Tuning(16, 2, 4, 4)
     assert L.art_set_tuning(h, ctypes.byref(ok)) == 0
-    assert L.art_get_tuning(h, ctypes.byref(t)) == 0 and (t.depth, t.subsets, t.waves) == (16, 2, 4)
+    assert L.art_get_tuning(h, ctypes.byref(t)) == 0
+    assert (t.depth, t.subsets, t.waves, t.interleave) == (16, 2, 4, 4)
     # sweep before set_fields is a state error, caught before any GPU work
     o = art.Outputs()
     assert L.art_sweep(h, 2, None, ctypes.c_float(0.0), ctypes.byref(o), None) == -4

@@ -22,7 +22,8 @@ def test_batch_matches_oracle_and_replays():
     for i, m in enumerate(meds):
         nb, nz, ny, nx = m.kappa.shape
         mesh = art.Mesh(nx, ny, nz)
-        mesh.set_tuning(depth=[8, 16, 5, 32, 3, 12][i % 6], subsets=1 + i % 2, waves=4)
+        mesh.set_tuning(depth=[8, 16, 5, 32, 3, 12][i % 6], subsets=1 + i % 2, waves=4,
+                        interleave=[1, 2, 4][i % 3])
         mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
         meshes.append(mesh)
     batch = art.Batch(meshes, [m.nside for m in meds], [m.gamma_w for m in meds], waves=4)
@@ -46,8 +47,7 @@ def test_batch_matches_oracle_and_replays():
         # eager work between replays
         x = torch.ones(1000, device="cuda").sum()
         assert float(x) == 1000.0
-    expect = sum(sum(1 for _ in [0]) for _ in meds)
-    assert st["segment_bins"] > 0 and expect == len(meds)
+    assert st["segment_bins"] > 0
     batch.close()
     for mesh in meshes:
         mesh.close()

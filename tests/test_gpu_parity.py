@@ -32,10 +32,10 @@ def _ragged(nbins=3, nside=2, shape=(19, 23, 17), seed=5, I_bc=0.3, name="ragged
     return m
 
 
-@pytest.mark.parametrize("tuning", [None, dict(depth=8, subsets=1, waves=4),
-                                    dict(depth=5, subsets=3, waves=2),
-                                    dict(depth=3, subsets=2, waves=1),
-                                    dict(depth=64, subsets=1, waves=16)])
+@pytest.mark.parametrize("tuning", [None, dict(depth=8, subsets=1, waves=4, interleave=1),
+                                    dict(depth=5, subsets=3, waves=2, interleave=4),
+                                    dict(depth=3, subsets=2, waves=1, interleave=2),
+                                    dict(depth=64, subsets=1, waves=8, interleave=4)])
 def test_ragged_multibin_tilings(tuning):
     """Several blocks with ragged tails, 3 bins, a vacuum cell, I_bc > 0; every
     launch shape must give the oracle's result."""
