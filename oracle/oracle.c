@@ -416,3 +416,112 @@ int oracle_sweep(int nx, int ny, int nz, double h, int nbins,
     free(n); free(num); free(den); free(numL); free(denL); free(exL); free(hits);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The same sums as oracle_sweep, at chosen cells only (Sect. 2.2, eq       */
+/* averaged_intensity; readings Q3/Q4): for each direction, the rays that   */
+/* cross cell c are found by enumerating every lattice ray whose transverse */
+/* position can reach the cell's box over the cell's depth interval, and    */
+/* each is marched from its entry up to the cell.  This lets single cells   */
+/* of a large mesh be checked without sweeping all of it.                   */
+/*   jin_sum[b][i], ex_sum[b][i] for cells[i] (x-fastest cell index).       */
+/* Returns 0 on success.                                                    */
+/* ------------------------------------------------------------------------ */
+int oracle_cells(int nx, int ny, int nz, double h, int nbins,
+                 const double *kappa, const double *S,
+                 int nside, int d_begin, int d_end, double I_bc,
+                 const int64_t *cells, int ncells, double *jin_sum, double *ex_sum,
+                 int nthreads)
+{
+    const int N[3] = {nx, ny, nz};
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const int nd = oracle_ndirs(nside);
+    if (nx < 1 || ny < 1 || nz < 1 || nbins < 1 || nside < 1 || !(h > 0.0)) return -1;
+    if (d_begin < 0 || d_end > nd || d_begin > d_end || ncells < 0) return -1;
+    for (int i = 0; i < ncells; ++i)
+        if (cells[i] < 0 || cells[i] >= ncell) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double *n = (double *)malloc(sizeof(double) * 3 * nd);
+    if (!n) return -2;
+    oracle_directions(nside, n);
+    const int mc = max_crossings(N);
+    int failed = 0;
+
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : failed)
+    for (int i = 0; i < ncells; ++i) {
+        const int64_t cid = cells[i];
+        const int cx[3] = {(int)(cid % nx), (int)((cid / nx) % ny), (int)(cid / ((int64_t)nx * ny))};
+        double *buf = (double *)malloc(sizeof(double) * mc);
+        int *cell = (int *)malloc(sizeof(int) * mc);
+        double *dl = (double *)malloc(sizeof(double) * mc);
+        double *s0 = (double *)malloc(sizeof(double) * mc);
+        double *I = (double *)malloc(sizeof(double) * nbins);
+        double *num = (double *)malloc(sizeof(double) * nbins);
+        double *den = (double *)malloc(sizeof(double) * nbins);
+        double *numL = (double *)malloc(sizeof(double) * nbins);
+        double *exL = (double *)malloc(sizeof(double) * nbins);
+        if (!buf || !cell || !dl || !s0 || !I || !num || !den || !numL || !exL) {
+            failed = 1;
+        } else {
+            for (int b = 0; b < nbins; ++b) {
+                if (jin_sum) jin_sum[(int64_t)b * ncells + i] = 0.0;
+                if (ex_sum) ex_sum[(int64_t)b * ncells + i] = 0.0;
+            }
+            for (int d = d_begin; d < d_end; ++d) {
+                odir_t g;
+                dir_geom(n + 3 * d, &g);
+                /* depth interval of the cell's slab along the dominant axis */
+                double slo = g.sig > 0 ? cx[g.a] : (double)N[g.a] - cx[g.a] - 1.0;
+                double shi = slo + 1.0;
+                /* lattice rays whose transverse position can be inside the cell */
+                const double b0 = g.tb * slo, b1 = g.tb * shi, c0 = g.tc * slo, c1 = g.tc * shi;
+                const int jlo = (int)floor(cx[g.b] - 0.5 - fmax(b0, b1)) - 1;
+                const int jhi = (int)ceil(cx[g.b] + 0.5 - fmin(b0, b1)) + 1;
+                const int klo = (int)floor(cx[g.c] - 0.5 - fmax(c0, c1)) - 1;
+                const int khi = (int)ceil(cx[g.c] + 0.5 - fmin(c0, c1)) + 1;
+                double denL = 0.0;
+                for (int b = 0; b < nbins; ++b) num[b] = den[b] = numL[b] = exL[b] = 0.0;
+                for (int k = klo; k <= khi; ++k) {
+                    for (int j = jlo; j <= jhi; ++j) {
+                        const int ns = ray_segments(&g, N, h, j, k, buf, cell, dl, s0);
+                        int hit = -1;
+                        for (int q = 0; q < ns; ++q)
+                            if (cell[q] == cid) { hit = q; break; }
+                        if (hit < 0) continue;
+                        for (int b = 0; b < nbins; ++b) I[b] = I_bc;
+                        for (int q = 0; q <= hit; ++q) {
+                            const int64_t c = cell[q];
+                            for (int b = 0; b < nbins; ++b) {
+                                const int64_t bc = (int64_t)b * ncell + c;
+                                const double dtau = kappa[bc] * dl[q];          /* eq rt */
+                                const double one_m_e = -expm1(-dtau);
+                                const double phi = dtau > 0.0 ? one_m_e / dtau : 1.0;
+                                if (q == hit) {                                 /* eq averaged_intensity */
+                                    num[b] += dtau * I[b] * phi;
+                                    den[b] += dtau;
+                                    numL[b] += dl[q] * I[b] * phi;              /* Q3 */
+                                    exL[b] += dl[q] * (1.0 - phi);              /* Q4 */
+                                }
+                                I[b] = I[b] * exp(-dtau) + S[bc] * one_m_e;     /* eq rt */
+                            }
+                        }
+                        denL += dl[hit];
+                    }
+                }
+                for (int b = 0; b < nbins; ++b) {
+                    double ave_in;
+                    if (den[b] > 0.0) ave_in = num[b] / den[b];
+                    else ave_in = denL > 0.0 ? numL[b] / denL : 0.0;
+                    if (jin_sum) jin_sum[(int64_t)b * ncells + i] += ave_in;
+                    if (ex_sum && denL > 0.0) ex_sum[(int64_t)b * ncells + i] += exL[b] / denL;
+                }
+            }
+        }
+        free(buf); free(cell); free(dl); free(s0); free(I);
+        free(num); free(den); free(numL); free(exL);
+    }
+    free(n);
+    return failed ? -2 : 0;
+}

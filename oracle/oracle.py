@@ -50,6 +50,10 @@ def lib():
         L.oracle_sweep.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp] +
                                    [ctypes.c_int] * 3 + [ctypes.c_double, dp, dp, dp, dp,
                                                          ctypes.c_int])
+        L.oracle_cells.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp] +
+                                   [ctypes.c_int] * 3 + [ctypes.c_double,
+                                                         ctypes.POINTER(ctypes.c_int64),
+                                                         ctypes.c_int, dp, dp, ctypes.c_int])
         _lib = L
     return _lib
 
@@ -152,3 +156,41 @@ def sweep(kappa, S, nside: int, gamma_w=None, h: float = 1.0, I_bc: float = 0.0,
     Gamma = np.tensordot(g, J_in + S64, axes=(0, 0))
     return dict(J_in=J_in, J=J, J_exact=J_exact, Gamma=Gamma, exit_sum=raw["exit_sum"],
                 nseg=raw["nseg"], inv_err=raw["inv_err"], max_hits=raw["max_hits"], nd=nd)
+
+
+def cells(kappa, S, nside: int, cell_idx, gamma_w=None, h: float = 1.0, I_bc: float = 0.0,
+          d_range=None, nthreads: int = 0):
+    """The outputs of `sweep` at chosen cells only, float64.
+
+    cell_idx: flat x-fastest cell indices.  Each cell's direction sums are
+    formed from the rays that cross it, each marched from its entry up to
+    the cell (same definitions as the full sweep).  Returns dict with
+    jin_sum, ex_sum (nbins, ncells) over d_range, and, for the full
+    direction set, J_in, J, J_exact (nbins, ncells) and Gamma (ncells,).
+    """
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    if kappa.ndim == 3:
+        kappa = kappa[None]
+        S = S[None]
+    nb, nz, ny, nx = kappa.shape
+    idx = np.ascontiguousarray(cell_idx, dtype=np.int64).ravel()
+    nd = ndirs(nside)
+    d0, d1 = d_range if d_range is not None else (0, nd)
+    jin = np.zeros((nb, idx.size))
+    ex = np.zeros((nb, idx.size))
+    rc = lib().oracle_cells(nx, ny, nz, float(h), nb, _dp(kappa), _dp(S), nside, d0, d1,
+                            float(I_bc), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            idx.size, _dp(jin), _dp(ex), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_cells failed ({rc})")
+    out = dict(jin_sum=jin, ex_sum=ex, nd=nd, d_range=(d0, d1))
+    if (d0, d1) == (0, nd):
+        S_c = S.reshape(nb, -1)[:, idx]
+        J_in = jin / nd
+        out["J_in"] = J_in
+        out["J"] = J_in + S_c
+        out["J_exact"] = J_in + S_c * (ex / nd)
+        g = np.ones(nb) if gamma_w is None else np.asarray(gamma_w, dtype=np.float64)
+        out["Gamma"] = np.tensordot(g, J_in + S_c, axes=(0, 0))
+    return out
