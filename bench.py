@@ -16,7 +16,7 @@ of the march from the committed rocprofv3 counter summary, null when that
 summary was taken on a different march kernel source.
 
 cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
-bounded sample of the same workload: 24 of the 768 directions (around the
+bounded sample of the same workload: 36 of the 768 directions (around the
 equator) over the full mesh and all four bins.
 """
 from __future__ import annotations
@@ -43,7 +43,7 @@ def march_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(nlaunch_bytes_scale):
+def load_traffic():
     """HBM bytes per sweep of the march from the committed counter summary,
     or None when absent or taken on another march source."""
     try:
@@ -71,18 +71,27 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
 
 
-def _pmc_sums(csv_path, counter):
-    """Per-kernel-name sums of one counter over all dispatches (KiB as reported)."""
-    import csv
+def _pmc_sums(path, counter):
+    """Per-kernel-name sums of one counter over all dispatches (KiB as
+    reported), from a rocprofv3 --pmc output: its SQLite database
+    (*_results.db) or its counter_collection CSV."""
     import collections
     out = collections.defaultdict(float)
     calls = collections.Counter()
-    with open(csv_path) as f:
-        for r in csv.DictReader(f):
-            if r["Counter_Name"] != counter:
-                continue
-            out[r["Kernel_Name"]] += float(r["Counter_Value"])
-            calls[r["Kernel_Name"]] += 1
+    if path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(path)
+        rows = con.execute("select kernel_name, value from counters_collection "
+                           "where counter_name = ?", (counter,)).fetchall()
+        con.close()
+    else:
+        import csv
+        with open(path) as f:
+            rows = [(r["Kernel_Name"], r["Counter_Value"]) for r in csv.DictReader(f)
+                    if r["Counter_Name"] == counter]
+    for name, val in rows:
+        out[name] += float(val)
+        calls[name] += 1
     return out, calls
 
 
@@ -109,7 +118,7 @@ def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sweeps):
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline(medium, d_range=(372, 396)):
+def cpu_baseline(medium, d_range=(366, 402)):
     import numpy as np
     from oracle import oracle as O
     threads = min(16, os.cpu_count() or 1)
@@ -132,9 +141,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only the counter-calibration copy of 1 GiB")
-    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
-                                                        "COPY_WRITE_CSV"),
-                    help="write the march traffic summary from rocprofv3 --pmc CSVs")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write the march traffic summary from rocprofv3 --pmc outputs "
+                         "(*_results.db or counter_collection.csv)")
     ap.add_argument("--sweeps", type=int, default=1, help="sweeps in the --traffic-from runs")
     args = ap.parse_args()
     if args.traffic_from:
@@ -183,7 +192,13 @@ def main():
     alg_bytes = 8.0 * nx * ny * nz * nd * nb
     march_s = (sum(march_ms) / len(march_ms)) / 1e3
     achieved = alg_bytes / march_s / 1e9
-    traffic = load_traffic(None)
+    traffic = load_traffic()
+    # the march is one launch per wavefront index: the largest block-index sum
+    # over the three dominant axes, plus one
+    tn = mesh.get_tuning()
+    dims = (nx, ny, nz)
+    launches = max(-(-dims[a] // tn["depth"]) + sum(-(-dims[q] // 8) for q in range(3) if q != a) - 2
+                   for a in range(3))
     rec = {
         "metric": "ray-segment updates/s (segment-bin updates per second) of the plain FP32 sweep",
         "value": value,
@@ -202,9 +217,15 @@ def main():
                    "segments_per_bin": segs[-1], "sweep_ms_event": sum(sweep_ms) / len(sweep_ms),
                    "march_ms_event": sum(march_ms) / len(march_ms)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic / launches,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "algorithmic_bytes_per_launch": alg_bytes / launches,
                      "algorithmic_bytes_per_sweep": alg_bytes,
-                     "kernel": "art_march_kernel<4> (all wavefront launches of one sweep)"},
+                     "launches_per_sweep": launches,
+                     "avg_launch_ms": 1e3 * march_s / launches,
+                     "kernel": f"art_march_kernel<{nb},{tn['interleave']}> "
+                               "(achieved = algorithmic bytes per launch / average launch time)"},
         "cpu_baseline": None,
     }
     mesh.close()

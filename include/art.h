@@ -63,7 +63,8 @@ typedef struct {
  * cut into blocks of 8 x 8 columns (the two other axes) by `depth` cells
  * along a; one workgroup of `waves` 64-lane waves marches one block for one
  * bucket of directions (one of `subsets` parts of a dominant-axis x octant
- * group). */
+ * group).  A new mesh starts with {depth 8, subsets 1, waves 1, interleave 4},
+ * the fastest shape measured for a 256^3 mesh with 768 directions and 4 bins. */
 typedef struct {
     int depth;        /* cells of a block along the dominant axis, 1..256 */
     int subsets;      /* buckets per (dominant axis, octant) group, 1..64 */

@@ -64,7 +64,7 @@ struct art_mesh {
     double h = 1.0;
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
-    art_tuning tune{32, 1, 8, 4};
+    art_tuning tune{8, 1, 1, 4};
 
     float4 *fields = nullptr; size_t fields_cap = 0;
     int *bad = nullptr; size_t bad_cap = 0;
@@ -74,7 +74,7 @@ struct art_mesh {
     int *order = nullptr; size_t order_cap = 0;
     int *bucket_start = nullptr; size_t bs_cap = 0;
     float *state = nullptr; size_t state_cap = 0;
-    float4 *geo = nullptr; size_t geo_cap = 0;
+    uint4 *geo = nullptr; size_t geo_cap = 0;
     float *acc = nullptr; size_t acc_cap = 0;
 
     // schedule (depends on shape and tuning only)

@@ -163,13 +163,15 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
 }
 
 
-// Per-(direction, slab) crossing table used by the march: for slab i of the
-// depth axis, the transverse lattice shift B(i) = floor(1/2 + t i) of every
-// ray changes by sh = B(i+1) - B(i) in {-1, 0, 1} at depth fraction
-// f = (X - (1/2 + t i)) / t (X the plane crossed), per transverse axis.
-// Entry: {f_b, f_c, sh_b, sh_c} (f = 2 when there is no crossing).
+// Per-(direction, slab) crossing table used by the march.  For slab i of the
+// depth axis the transverse lattice shift B(i) = floor(1/2 + t i) of every ray
+// changes by sh = B(i+1) - B(i) in {-1, 0, 1}, at depth fraction
+// f = (X - (1/2 + t i)) / t (X the plane crossed), per transverse axis.  The
+// entry holds the lengths of the slab's (up to three) segments in crossing
+// order and a code: bits 0-1 sh_b + 1, bits 2-3 sh_c + 1, bit 4 "b-plane
+// crossed first", bits 5-6 number of segments of positive length.
 __global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__ dirs, int nx, int ny,
-                                                      int nz, int stride, float4 *__restrict__ geo)
+                                                      int nz, int stride, uint4 *__restrict__ geo)
 {
     const int d = blockIdx.x;
     const ArtDir &D = dirs[d];
@@ -187,14 +189,29 @@ __global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__
         double fb = 2.0, fc = 2.0;
         if (shb) fb = fmin(1.0, fmax(0.0, ((double)(shb > 0 ? Bb + 1 : Bb) - xb0) * rtb));
         if (shc) fc = fmin(1.0, fmax(0.0, ((double)(shc > 0 ? Bc + 1 : Bc) - xc0) * rtc));
-        geo[(long long)d * stride + i] = make_float4((float)fb, (float)fc, (float)shb, (float)shc);
+        const bool b_first = fb <= fc;
+        float s1, s2, s3;
+        if (shb && shc) {
+            const float f1 = (float)fmin(fb, fc), f2 = (float)fmax(fb, fc);
+            s1 = f1; s2 = f2 - f1; s3 = 1.0f - f2;
+        } else if (shb || shc) {
+            const float f1 = (float)(shb ? fb : fc);
+            s1 = f1; s2 = 1.0f - f1; s3 = 0.0f;
+        } else {
+            s1 = 1.0f; s2 = 0.0f; s3 = 0.0f;
+        }
+        const unsigned npos = (s1 > 0.f) + (s2 > 0.f) + (s3 > 0.f);
+        const unsigned code = (unsigned)(shb + 1) | ((unsigned)(shc + 1) << 2) |
+                              ((unsigned)b_first << 4) | (npos << 5);
+        geo[(long long)d * stride + i] =
+            make_uint4(__float_as_uint(s1), __float_as_uint(s2), __float_as_uint(s3), code);
     }
 }
 
 }  // namespace
 
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
-                           int subsets, ArtDir *dirs, int *order, int *bucket_start, float4 *geo,
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start, uint4 *geo,
                            int geo_stride, hipStream_t stream)
 {
     hipLaunchKernelGGL(art_dirs_kernel, dim3(1), dim3(256), 0, stream, nside, nx, ny, nz, nb,

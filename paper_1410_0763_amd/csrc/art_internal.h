@@ -32,7 +32,7 @@ struct ArtMeshDesc {
     const ArtDir *dirs;        // [N_d]
     const int *order;          // direction indices grouped by bucket
     const int *bucket_start;   // [nbuckets + 1]
-    const float4 *geo;         // [N_d][geo_stride] slab crossing table
+    const uint4 *geo;          // [N_d][geo_stride] slab crossing table
     long long ncell;
     int geo_stride;            // max(nx, ny, nz)
     int interleave;            // directions marched together by one wave (1, 2, 4)
@@ -55,7 +55,7 @@ struct ArtItem {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
-                           int subsets, ArtDir *dirs, int *order, int *bucket_start, float4 *geo,
+                           int subsets, ArtDir *dirs, int *order, int *bucket_start, uint4 *geo,
                            int geo_stride, hipStream_t stream);
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,

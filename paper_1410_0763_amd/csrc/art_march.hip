@@ -43,9 +43,12 @@
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v3f __attribute__((ext_vector_type(3)));   // 16-byte stride, 12-byte loads
 // Global-address-space views: pointers read from the descriptor are generic,
-// and generic (flat) loads would share the LDS wait counter.
-typedef __attribute__((address_space(1))) const v4f g_f4;
+// and generic (flat) loads would share the LDS wait counter.  The field
+// records are read as three floats: a dead fourth register would be reused
+// at once and force a wait for the whole load (write-after-write).
+typedef __attribute__((address_space(1))) const v3f g_f3;
 typedef __attribute__((address_space(1))) float g_f;
 
 __device__ __forceinline__ void lds_add(float *p, float v)
@@ -61,7 +64,7 @@ __device__ __forceinline__ float lane_get(float v, int src)
 
 // One segment of depth length ds in the lane's cell, for every bin.
 template <int NB>
-__device__ __forceinline__ void segment(const v4f *F, float ds, float invw, float w, float *I,
+__device__ __forceinline__ void segment(const v3f *F, float ds, float invw, float w, float *I,
                                         float *a1, float *a2)
 {
     const float dl = ds * invw;
@@ -103,14 +106,15 @@ __device__ __forceinline__ float shift_next(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
 }
 
-typedef __attribute__((address_space(4))) const v4f c_f4;
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4u c_u4;
 typedef __attribute__((address_space(4))) const ArtDir c_dir;
 typedef __attribute__((address_space(4))) const int c_int;
 
 template <int NB, int K>
 __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restrict__ items,
-                                                         const ArtMeshDesc *__restrict__ meshes,
-                                                         unsigned int *__restrict__ seg_count)
+                                                        const ArtMeshDesc *__restrict__ meshes,
+                                                        unsigned int *__restrict__ seg_count)
 {
     extern __shared__ __align__(16) float lds[];
     const ArtItem it = items[blockIdx.x];
@@ -147,14 +151,23 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const int col = lane & 7, row = lane >> 3;
     const int gb = lo_b + col, gc = lo_c + row;
     const bool in_dom = gb < Nb && gc < Nc;
+    // What a lane does when all rays move one column (b) or row (c) forward
+    // (+1) or back (-1): its ray leaves the tile or the mesh (store the
+    // state), it takes the neighbour lane's ray, or it loads a ray arriving
+    // from the next tile (otherwise a fresh ray enters the mesh with I_bc).
+    const bool lbp = col == 7 || gb + 1 >= Nb, tbp = col >= 1, ibp = col == 0 && gb >= 1;
+    const bool lbm = col == 0, tbm = col <= 6 && gb + 1 < Nb, ibm = col == 7 && gb + 1 < Nb;
+    const bool lcp = row == 7 || gc + 1 >= Nc, tcp = row >= 1, icp = row == 0 && gc >= 1;
+    const bool lcm = row == 0, tcm = row <= 6 && gc + 1 < Nc, icm = row == 7 && gc + 1 < Nc;
+
     const int V = depth * 64;                             // cells of one block
     float *accl = lds;
     for (int i = threadIdx.x; i < NB * 2 * V; i += blockDim.x) accl[i] = 0.0f;
     __syncthreads();
 
-    g_f4 *fields = (g_f4 *)M.fields;
+    g_f3 *fields = (g_f3 *)M.fields;
     g_f *state = (g_f *)M.state;
-    c_f4 *geo = (c_f4 *)M.geo;
+    c_u4 *geo = (c_u4 *)M.geo;
     c_dir *dirs = (c_dir *)M.dirs;
     c_int *order = (c_int *)M.order;
     const int gstride = M.geo_stride;
@@ -162,15 +175,45 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const long long xa0 = sig_neg ? Na - 1 - d0 : d0;
     const long long cell0 = xa0 * sa + gb * sb + gc * sc;
     const long long dcell = sig_neg ? -sa : sa;
-    unsigned int nseg = 0;
+    unsigned int sseg = 0;   // segments of positive length per in-mesh lane (wave-uniform)
 
     // A wave marches K directions of the bucket together: q0 + m * nwave, m < K.
+    // Software pipeline: at the top of slab t every load slab t+1 needs is
+    // issued (its fields, the rays that enter the tile during it, and the
+    // crossing table of slab t+2); they land while slab t is marched and are
+    // rotated into place at its end.  All of these loads are issued by every
+    // lane from a valid address (lanes that need no value read the
+    // direction's first state slot or cell 0): a load under a branch, or a
+    // dead register of a vector load, makes the compiler wait for it at once.
     for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
         bool act[K];
-        int dix[K], Bb[K], Bc[K], j0[K], nj[K], k0[K];
-        long long soff[K];
+        int dix[K], njm[K];
+        long long cur[K];       // state slot of the lane's current ray
+        long long soff[K];      // first state slot of the direction
         float invw[K], wdir[K];
         float I[K][NB];
+        float ib[K][NB], ic[K][NB];   // rays entering the tile during the current slab
+        bool needb[K], needc[K];
+        v4u gA[K], gB[K];             // crossing tables of the current and the next slab
+        // Rays entering the tile during the slab with crossing table g, for a
+        // lane whose ray is in slot `at` at the top of that slab.
+        auto load_incoming = [&](int m, const v4u &g, long long at, float *jb, float *jc,
+                                 bool &nbm, bool &ncm) {
+            const unsigned code = g.w;
+            const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
+            const bool b_first = (code >> 4) & 1u;
+            const long long dB = (long long)shb * NB;
+            const long long dC = (long long)shc * njm[m] * NB;
+            nbm = shb && in_dom && (shb > 0 ? ibp : ibm);
+            ncm = shc && in_dom && (shc > 0 ? icp : icm);
+            const long long slb = nbm ? at - (b_first ? 0 : dC) - dB : soff[m];
+            const long long slc = ncm ? at - (b_first ? dB : 0) - dC : soff[m];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                jb[b] = state[slb + b];
+                jc[b] = state[slc + b];
+            }
+        };
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             const int q = q0 + m * nwave;
@@ -179,153 +222,153 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             const c_dir &D = dirs[dix[m]];
             const double tb = ab == 0 ? D.beta[0] : D.beta[1];
             const double tc = ac == 1 ? D.beta[1] : D.beta[2];
-            Bb[m] = (int)floor(fma(tb, (double)d0, 0.5));
-            Bc[m] = (int)floor(fma(tc, (double)d0, 0.5));
-            j0[m] = D.j0; nj[m] = D.nj; k0[m] = D.k0;
+            const int Bb = (int)floor(fma(tb, (double)d0, 0.5));
+            const int Bc = (int)floor(fma(tc, (double)d0, 0.5));
+            njm[m] = D.nj;
             soff[m] = D.state_off;
+            cur[m] = D.state_off + ((long long)(gc - Bc - D.k0) * D.nj + (gb - Bb - D.j0)) * NB;
             invw[m] = (float)D.invw;
             wdir[m] = (float)D.w;
+            // rays entering through the top face come from the block above
+            const bool from_above = in_dom && d0 > 0;
+            const long long s0 = from_above ? cur[m] : soff[m];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) I[m][b] = I_bc;
-            if (act[m] && in_dom && d0 > 0) {
-                const long long sl = soff[m] + ((long long)(gc - Bc[m] - k0[m]) * nj[m] + (gb - Bb[m] - j0[m])) * NB;
+            for (int b = 0; b < NB; ++b) I[m][b] = state[s0 + b];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) I[m][b] = state[sl + b];
-            }
+            for (int b = 0; b < NB; ++b) I[m][b] = from_above ? I[m][b] : I_bc;
+            const long long gbase = (long long)dix[m] * gstride;
+            gA[m] = geo[gbase + d0];
+            gB[m] = geo[gbase + min(d0 + 1, Na - 1)];
+            load_incoming(m, gA[m], cur[m], ib[m], ic[m], needb[m], needc[m]);
         }
-        v4f F[NB];
+        // lanes outside the mesh read cell 0 (their results are never stored)
+        v3f F[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) F[b] = v4f{0.f, 0.f, 0.f, 0.f};
-        if (in_dom) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) F[b] = fields[cell0 * NB + b];
-        }
+        for (int b = 0; b < NB; ++b) F[b] = fields[(in_dom ? cell0 : 0) * NB + b];
         long long cell = cell0;
 
         for (int t = 0; t < nslab; ++t) {
             const int i = d0 + t;
-            // prefetch the next slab's fields
-            v4f Fn[NB];
+            // prefetch for slab t+1 (past the last slab: harmless repeats)
+            const long long ncell = in_dom ? (t + 1 < nslab ? cell + dcell : cell) : 0;
+            v3f Fn[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) Fn[b] = v4f{0.f, 0.f, 0.f, 0.f};
-            if (in_dom && t + 1 < nslab) {
+            for (int b = 0; b < NB; ++b) Fn[b] = fields[ncell * NB + b];
+            float ibn[K][NB], icn[K][NB];
+            bool needbn[K], needcn[K];
+            v4u gC[K];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) Fn[b] = fields[(cell + dcell) * NB + b];
+            for (int m = 0; m < K; ++m) {
+                const unsigned code = gA[m].w;
+                const long long at = cur[m] - (long long)((int)(code & 3u) - 1) * NB -
+                                     (long long)((int)((code >> 2) & 3u) - 1) * njm[m] * NB;
+                load_incoming(m, gB[m], at, ibn[m], icn[m], needbn[m], needcn[m]);
+                gC[m] = geo[(long long)dix[m] * gstride + min(i + 2, Na - 1)];
             }
             float a1[NB], a2[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) a1[b] = a2[b] = 0.0f;
-            unsigned int ns = 0;
 
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m]) continue;
-                const v4f g = geo[(long long)dix[m] * gstride + i];   // wave-uniform
-                const int shb = (int)g.z, shc = (int)g.w;
-                const float fb = g.x, fc = g.y;
-                const bool b_first = fb <= fc;
-                auto slot = [&](int Bb_, int Bc_) -> long long {
-                    return soff[m] + ((long long)(gc - Bc_ - k0[m]) * nj[m] + (gb - Bb_ - j0[m])) * NB;
-                };
-                // Rays arriving from outside this tile at the crossings.
-                const int srcb = col - shb, srcc = row - shc;
-                const bool b_mesh = gb - shb >= 0 && gb - shb < Nb;
-                const bool c_mesh = gc - shc >= 0 && gc - shc < Nc;
-                const bool b_tile = srcb >= 0 && srcb <= 7;
-                const bool c_tile = srcc >= 0 && srcc <= 7;
-                float inb[NB], inc[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) inb[b] = inc[b] = I_bc;
-                if (shb && in_dom && b_mesh && !b_tile) {
-                    const long long sl = slot(Bb[m] + shb, b_first ? Bc[m] : Bc[m] + shc);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) inb[b] = state[sl + b];
-                }
-                if (shc && in_dom && c_mesh && !c_tile) {
-                    const long long sl = slot(b_first ? Bb[m] + shb : Bb[m], Bc[m] + shc);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) inc[b] = state[sl + b];
-                }
+                const v4u g = gA[m];
+                const unsigned code = g.w;
+                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
+                const bool b_first = (code >> 4) & 1u;
+                const float s1 = __uint_as_float(g.x), s2 = __uint_as_float(g.y),
+                            s3 = __uint_as_float(g.z);
+                sseg += code >> 5;
+                const long long dB = (long long)shb * NB;
+                const long long dC = (long long)shc * njm[m] * NB;
                 float *Im = I[m];
                 // crossing of a b-plane: every ray moves from column gb to gb + shb
                 auto cross_b = [&]() {
-                    const bool leaves = col + shb < 0 || col + shb > 7 || gb + shb < 0 || gb + shb >= Nb;
-                    if (in_dom && leaves) {
-                        const long long sl = slot(Bb[m], Bc[m]);
+                    if (in_dom && (shb > 0 ? lbp : lbm)) {
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) state[sl + b] = Im[b];
+                        for (int b = 0; b < NB; ++b) state[cur[m] + b] = Im[b];
                     }
-                    const bool take = b_tile && b_mesh;
+                    const bool take = shb > 0 ? tbp : tbm;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float moved = shb > 0 ? shift_prev(Im[b]) : shift_next(Im[b]);
-                        Im[b] = take ? moved : inb[b];
+                        Im[b] = take ? moved : (needb[m] ? ib[m][b] : I_bc);
                     }
-                    Bb[m] += shb;
+                    cur[m] -= dB;
                 };
                 // crossing of a c-plane: every ray moves from row gc to gc + shc
                 auto cross_c = [&]() {
-                    const bool leaves = row + shc < 0 || row + shc > 7 || gc + shc < 0 || gc + shc >= Nc;
-                    if (in_dom && leaves) {
-                        const long long sl = slot(Bb[m], Bc[m]);
+                    if (in_dom && (shc > 0 ? lcp : lcm)) {
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) state[sl + b] = Im[b];
+                        for (int b = 0; b < NB; ++b) state[cur[m] + b] = Im[b];
                     }
-                    const int src = (min(7, max(0, srcc)) << 3) + col;
-                    const bool take = c_tile && c_mesh;
+                    const bool take = shc > 0 ? tcp : tcm;
+                    const int src = (min(7, max(0, row - shc)) << 3) + col;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float moved = lane_get(Im[b], src);
-                        Im[b] = take ? moved : inc[b];
+                        Im[b] = take ? moved : (needc[m] ? ic[m][b] : I_bc);
                     }
-                    Bc[m] += shc;
+                    cur[m] -= dC;
                 };
+                segment<NB>(F, s1, invw[m], wdir[m], Im, a1, a2);
                 if (shb && shc) {
-                    const float f1 = fminf(fb, fc), f2 = fmaxf(fb, fc);
-                    segment<NB>(F, f1, invw[m], wdir[m], Im, a1, a2);
                     if (b_first) cross_b(); else cross_c();
-                    segment<NB>(F, f2 - f1, invw[m], wdir[m], Im, a1, a2);
+                    segment<NB>(F, s2, invw[m], wdir[m], Im, a1, a2);
                     if (b_first) cross_c(); else cross_b();
-                    segment<NB>(F, 1.0f - f2, invw[m], wdir[m], Im, a1, a2);
-                    ns += (f1 > 0.f) + (f2 - f1 > 0.f) + (1.0f - f2 > 0.f);
+                    segment<NB>(F, s3, invw[m], wdir[m], Im, a1, a2);
                 } else if (shb || shc) {
-                    const float f1 = shb ? fb : fc;
-                    segment<NB>(F, f1, invw[m], wdir[m], Im, a1, a2);
                     if (shb) cross_b(); else cross_c();
-                    segment<NB>(F, 1.0f - f1, invw[m], wdir[m], Im, a1, a2);
-                    ns += (f1 > 0.f) + (1.0f - f1 > 0.f);
-                } else {
-                    segment<NB>(F, 1.0f, invw[m], wdir[m], Im, a1, a2);
-                    ns += 1;
+                    segment<NB>(F, s2, invw[m], wdir[m], Im, a1, a2);
                 }
             }
             if (in_dom) {
-                nseg += ns;
                 const int la = (sig_neg ? Na - 1 - i : i) - lo_a;
                 const int lc = la * 64 + lane;
+                if (nwave == 1) {
+                    // a single wave owns the block: plain read-modify-write
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    lds_add(&accl[(2 * b) * V + lc], a1[b]);
-                    lds_add(&accl[(2 * b + 1) * V + lc], a2[b]);
+                    for (int b = 0; b < NB; ++b) {
+                        accl[(2 * b) * V + lc] += a1[b];
+                        accl[(2 * b + 1) * V + lc] += a2[b];
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        lds_add(&accl[(2 * b) * V + lc], a1[b]);
+                        lds_add(&accl[(2 * b + 1) * V + lc], a2[b]);
+                    }
                 }
             }
+            // rotate the pipeline
             cell += dcell;
 #pragma unroll
             for (int b = 0; b < NB; ++b) F[b] = Fn[b];
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                gA[m] = gB[m];
+                gB[m] = gC[m];
+                needb[m] = needbn[m];
+                needc[m] = needcn[m];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    ib[m][b] = ibn[m][b];
+                    ic[m][b] = icn[m][b];
+                }
+            }
         }
         // rays leave through the block's far face (into the next block or out of the mesh)
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             if (act[m] && in_dom) {
-                const long long sl = soff[m] + ((long long)(gc - Bc[m] - k0[m]) * nj[m] + (gb - Bb[m] - j0[m])) * NB;
 #pragma unroll
-                for (int b = 0; b < NB; ++b) state[sl + b] = I[m][b];
+                for (int b = 0; b < NB; ++b) state[cur[m] + b] = I[m][b];
             }
         }
     }
 
     // workgroup total of marched segments of positive length (work accounting)
-    for (int off = 32; off > 0; off >>= 1) nseg += __shfl_down(nseg, off, 64);
+    const unsigned int nseg = sseg * (unsigned)__popcll(__ballot(in_dom));
     unsigned int *wg_count = reinterpret_cast<unsigned int *>(lds + NB * 2 * V);
     if (threadIdx.x == 0) *wg_count = 0u;
     __syncthreads();
