@@ -65,6 +65,7 @@ struct art_mesh {
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
     art_tuning tune{8, 1, 1, 4};
+    int mbd = 0, mbd_key[2] = {-1, -1};   // largest bucket (directions) for (nside, subsets)
 
     float4 *fields = nullptr; size_t fields_cap = 0;
     int *bad = nullptr; size_t bad_cap = 0;
@@ -157,6 +158,19 @@ int build_schedule(art_mesh *m)
     return ART_OK;
 }
 
+// Largest ray-slot count of one direction (the lattice covers the mesh's
+// cross-section widened by the depth on both sides).
+long long dir_slot_bound(const art_mesh *m)
+{
+    const long long N[3] = {m->nx, m->ny, m->nz};
+    long long worst = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        worst = std::max(worst, (N[b] + N[a] + 4) * (N[c] + N[a] + 4));
+    }
+    return worst;
+}
+
 long long state_bound(const art_mesh *m, int nd)
 {
     const long long N[3] = {m->nx, m->ny, m->nz};
@@ -165,7 +179,7 @@ long long state_bound(const art_mesh *m, int nd)
         const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
         worst = std::max(worst, (N[b] + N[a] + 4) * (N[c] + N[a] + 4));
     }
-    return worst * nd * m->nb;
+    return (worst + 1) * nd * m->nb;   // ray slots plus one boundary slot per direction
 }
 
 // Buffers and descriptor for a sweep at this nside (allocation is the only
@@ -173,6 +187,18 @@ long long state_bound(const art_mesh *m, int nd)
 int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
 {
     const int nd = 12 * nside * nside;
+    // the march addresses one bucket's ray states and one block's field
+    // records with 32-bit byte offsets from wave-uniform bases (a block spans
+    // at most depth - 1 + 7 + 7 steps of the largest cell stride nx ny)
+    if (m->mbd_key[0] != nside || m->mbd_key[1] != m->tune.subsets) {
+        m->mbd = art_max_bucket_dirs(nside, m->tune.subsets);
+        m->mbd_key[0] = nside;
+        m->mbd_key[1] = m->tune.subsets;
+    }
+    if ((long long)m->mbd * (dir_slot_bound(m) + 1) * m->nb * 4 >=
+            (1ll << 31) ||
+        (m->tune.depth + 14ll) * m->nx * m->ny * m->nb * 16 >= (1ll << 31))
+        return fail(ART_E_UNSUPPORTED, "mesh too large for 32-bit offsets within a bucket of directions or a block");
     const int nbk = 24 * m->tune.subsets;
     int rc;
     if ((rc = dev_alloc(&m->dirs, (size_t)nd, &m->dirs_cap))) return rc;
@@ -220,7 +246,8 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
         for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&m->ev[i]));
     HIPCHK(hipEventRecord(m->ev[0], st));
     HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
-                           m->dirs, m->order, m->bucket_start, m->geo, m->desc_host.geo_stride, st));
+                           m->dirs, m->order, m->bucket_start, m->geo, m->desc_host.geo_stride,
+                           m->state, I_bc, st));
     HIPCHK(hipEventRecord(m->ev[1], st));
     const int lds_floats = art_march_lds_floats(m->tune.depth, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
@@ -278,7 +305,7 @@ int batch_enqueue(art_batch *B, hipStream_t st)
         art_mesh *m = B->meshes[i];
         HIPCHK(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
                                m->tune.subsets, m->dirs, m->order, m->bucket_start, m->geo,
-                               m->desc_host.geo_stride, st));
+                               m->desc_host.geo_stride, m->state, m->desc_host.I_bc, st));
     }
     for (const auto &L : B->launches)
         HIPCHK(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,

@@ -16,13 +16,16 @@
 //
 // One workgroup: every thread builds directions; wave 0 then assigns buckets
 // and offsets with wave-wide prefix sums, so the result is deterministic.
+#include <algorithm>
+#include <cmath>
+
 #include "art_internal.h"
 
 #define ART_TIE 1e-12
 
 namespace {
 
-__device__ void healpix_ring(int nside, int d, double *n)
+__host__ __device__ void healpix_ring(int nside, int d, double *n)
 {
     const double N = (double)nside;
     const double PI = 3.14159265358979323846;
@@ -48,10 +51,8 @@ __device__ void healpix_ring(int nside, int d, double *n)
         phi = PI / (2.0 * ip) * (j - 0.5);
     }
     const double st = sqrt((1.0 - z) * (1.0 + z));
-    double sp, cp;
-    sincos(phi, &sp, &cp);
-    n[0] = st * cp;
-    n[1] = st * sp;
+    n[0] = st * cos(phi);
+    n[1] = st * sin(phi);
     n[2] = z;
     for (int q = 0; q < 3; ++q)
         if (fabs(n[q]) < ART_TIE) n[q] = 0.0;
@@ -108,13 +109,12 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
 
     // Wave 0: rank of each in-range direction within its group g = a * 8 +
     // octant (ballot prefix counts in index order), bucket = g * subsets +
-    // rank % subsets, and the state-buffer offsets (prefix sum of nj nk nb).
+    // rank % subsets, and the bucket-major order of the directions.
     const int lane = threadIdx.x;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int oct_count[24];
 #pragma unroll
     for (int g = 0; g < 24; ++g) oct_count[g] = 0;
-    long long off_base = 0;
     for (int base = 0; base < nd; base += 64) {
         const int d = base + lane;
         const bool valid = d < nd && d >= d_begin && d < d_end;
@@ -126,18 +126,10 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
             if (valid && oct == o) rank = oct_count[o] + __popcll(msk & below);
             oct_count[o] += __popcll(msk);
         }
-        long long mine = valid ? (long long)dirs[d].nj * dirs[d].nk * nb : 0;
-        long long incl = mine;
-        for (int sh = 1; sh < 64; sh <<= 1) {
-            const long long t = __shfl_up(incl, sh, 64);
-            if (lane >= sh) incl += t;
-        }
         if (d < nd) {
-            dirs[d].state_off = off_base + incl - mine;
             dirs[d].bucket = valid ? oct * subsets + rank % subsets : -1;
             dirs[d].pad = valid ? rank / subsets : 0;   // position inside the bucket
         }
-        off_base += __shfl(incl, 63, 64);
     }
     // Bucket sizes follow from the octant counts (identical in every lane),
     // so each lane derives the bucket offsets itself.
@@ -162,6 +154,36 @@ __global__ __launch_bounds__(256) void art_dirs_kernel(int nside, int nx, int ny
     }
 }
 
+
+// State-buffer offsets in bucket-major order (prefix sums of nj nk nb over
+// `order`), so that the directions of one bucket occupy one contiguous range.
+// Each direction's region starts with a boundary slot holding I_bc: the march
+// reads it for every ray that enters the mesh through a face.  One wave.
+__global__ __launch_bounds__(64) void art_state_kernel(int nb, const int *__restrict__ bucket_start,
+                                                       int nbuckets, const int *__restrict__ order,
+                                                       ArtDir *__restrict__ dirs,
+                                                       float *__restrict__ state, float I_bc)
+{
+    const int lane = threadIdx.x;
+    const int n = bucket_start[nbuckets];
+    long long off_base = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int p = base + lane;
+        const int d = p < n ? order[p] : -1;
+        const long long mine = d >= 0 ? (long long)dirs[d].nj * dirs[d].nk * nb + nb : 0;
+        long long incl = mine;
+        for (int sh = 1; sh < 64; sh <<= 1) {
+            const long long t = __shfl_up(incl, sh, 64);
+            if (lane >= sh) incl += t;
+        }
+        if (d >= 0) {
+            const long long first = off_base + incl - mine;
+            dirs[d].state_off = first + nb;
+            for (int b = 0; b < nb; ++b) state[first + b] = I_bc;
+        }
+        off_base += __shfl(incl, 63, 64);
+    }
+}
 
 // Per-(direction, slab) crossing table used by the march.  For slab i of the
 // depth axis the transverse lattice shift B(i) = floor(1/2 + t i) of every ray
@@ -212,13 +234,36 @@ __global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__
 
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
                            int subsets, ArtDir *dirs, int *order, int *bucket_start, uint4 *geo,
-                           int geo_stride, hipStream_t stream)
+                           int geo_stride, float *state, float I_bc, hipStream_t stream)
 {
     hipLaunchKernelGGL(art_dirs_kernel, dim3(1), dim3(256), 0, stream, nside, nx, ny, nz, nb,
                        d_begin, d_end, subsets, dirs, order, bucket_start);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(art_state_kernel, dim3(1), dim3(64), 0, stream, nb, bucket_start,
+                       24 * subsets, order, dirs, state, I_bc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(art_geo_kernel, dim3(12 * nside * nside), dim3(256), 0, stream, dirs, nx, ny,
                        nz, geo_stride, geo);
     return hipGetLastError();
+}
+
+// Largest number of directions in one bucket for this direction set (the
+// same classification as the generator, on the host).
+int art_max_bucket_dirs(int nside, int subsets)
+{
+    int cnt[24] = {0};
+    const int nd = 12 * nside * nside;
+    for (int d = 0; d < nd; ++d) {
+        double n[3];
+        healpix_ring(nside, d, n);
+        const double m = fmax(fabs(n[0]), fmax(fabs(n[1]), fabs(n[2])));
+        const int a = fabs(n[0]) >= m - ART_TIE ? 0 : (fabs(n[1]) >= m - ART_TIE ? 1 : 2);
+        const int oct = (n[0] < 0.0 ? 1 : 0) | (n[1] < 0.0 ? 2 : 0) | (n[2] < 0.0 ? 4 : 0);
+        ++cnt[a * 8 + oct];
+    }
+    int worst = 0;
+    for (int g = 0; g < 24; ++g) worst = std::max(worst, (cnt[g] + subsets - 1) / subsets);
+    return worst;
 }

@@ -56,7 +56,7 @@ struct ArtItem {
 // Kernel launchers (defined in the .hip files).
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
                            int subsets, ArtDir *dirs, int *order, int *bucket_start, uint4 *geo,
-                           int geo_stride, hipStream_t stream);
+                           int geo_stride, float *state, float I_bc, hipStream_t stream);
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,
                             hipStream_t stream);
@@ -69,5 +69,6 @@ hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int n
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
 hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream);
+int art_max_bucket_dirs(int nside, int subsets);
 int art_march_max_lds_bytes();
 int art_march_lds_floats(int depth, int nb);

@@ -20,12 +20,29 @@
 // depth s, so at the top of slab i it is in column (j + B_b(i), k + B_c(i)),
 // B(i) = floor(1/2 + t i): the lattice shift is the same for every ray.  Hence
 // the whole wave shares one segment pattern per slab: at most one b- and one
-// c-plane crossing, at depth fractions f_b, f_c, splitting the slab into up to
-// three segments.  At a crossing every ray moves to the neighbouring column,
-// i.e. the intensities move one lane over (ds_bpermute); edge lanes hand rays
-// to and from the neighbouring blocks through the state buffer.  A lane thus
-// reads its own cell's fields once per slab and adds its contributions to its
-// own cell once per slab.
+// c-plane crossing, splitting the slab into up to three segments.  At a
+// crossing every ray moves to the neighbouring column, i.e. the intensities
+// move one lane over (DPP row shift along b, ds_bpermute along c); edge lanes
+// hand rays to and from the neighbouring blocks through the state buffer.  A
+// lane reads its own cell's fields once per slab and adds its contributions to
+// its own cell once per slab.  The per-(direction, slab) pattern comes from a
+// table built once per sweep and is read with scalar loads, so every branch on
+// it is a scalar branch (its segment lengths stay in vector registers).
+//
+// A wave marches K directions at once and orders a slab's work by phase: the
+// first segment of every direction, then the first crossing and second
+// segment of every direction, then the second crossing and third segment.
+// The rays that enter the tile during the slab are loaded at its top and are
+// first needed after the K first segments; the next slab's fields are loaded
+// one slab ahead.
+//
+// Memory is addressed through buffer descriptors with 32-bit byte offsets
+// (wave-uniform bases in scalar registers): a direction's state region, and
+// the block's field records.  A lane that must not store (it is not at the
+// tile edge the rays leave through, or outside the mesh) stores to an offset
+// beyond the descriptor's range, which the hardware drops.  Each direction's
+// state region starts with a boundary slot holding I_bc, read by every lane
+// whose ray enters through a mesh face (and by lanes that need no ray).
 //
 // Per segment of depth length ds (path length dL = ds / |n_a| cells), per bin
 // (eq rt and eq path_averaged_intensity):
@@ -42,14 +59,88 @@
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v3f __attribute__((ext_vector_type(3)));   // 16-byte stride, 12-byte loads
-// Global-address-space views: pointers read from the descriptor are generic,
-// and generic (flat) loads would share the LDS wait counter.  The field
-// records are read as three floats: a dead fourth register would be reused
-// at once and force a wait for the whole load (write-after-write).
-typedef __attribute__((address_space(1))) const v3f g_f3;
+typedef float v3f __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef __attribute__((address_space(1))) float g_f;
+typedef __attribute__((address_space(1))) const u32x4 g_u4;
+typedef __attribute__((address_space(4))) const ArtDir c_dir;
+typedef __attribute__((address_space(4))) const int c_int;
+
+// Buffer descriptor of `bytes` bytes at p (word 3 as for every gfx9 part:
+// 32-bit data format, no swizzle).  Accesses at offsets >= bytes read 0 and
+// write nothing.
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+// A byte offset no descriptor here reaches (every range is below 2^31 bytes).
+#define ART_OOB 0x80000000u
+
+// The NB floats of a ray-state slot.
+template <int NB>
+__device__ __forceinline__ void load_slot(rsrc_t r, unsigned off, float *v)
+{
+    if constexpr (NB == 4) {
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y);
+        v[2] = __uint_as_float(x.z); v[3] = __uint_as_float(x.w);
+    } else if constexpr (NB == 3) {
+        const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+        v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y); v[2] = __uint_as_float(x.z);
+    } else if constexpr (NB == 2) {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y);
+    } else {
+        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ void store_slot(rsrc_t r, unsigned off, const float *v)
+{
+    if constexpr (NB == 4) {
+        const u32x4 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                         __float_as_uint(v[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, 0);
+    } else if constexpr (NB == 3) {
+        const u32x3 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
+        __builtin_amdgcn_raw_buffer_store_b96(x, r, off, 0, 0);
+    } else if constexpr (NB == 2) {
+        const u32x2 x = {__float_as_uint(v[0]), __float_as_uint(v[1])};
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, off, 0, 0);
+    }
+}
+
+// Field record {kappa h, 1/(kappa h), S} of one (cell, bin): 12 bytes of a
+// 16-byte record (a dead fourth register would be reused at once and force a
+// wait for the whole load).
+__device__ __forceinline__ v3f load_field(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(v3f, __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0));
+}
+
+// A wave-uniform value kept in a vector register: per-direction constants
+// that only feed vector arithmetic would otherwise occupy scalar registers,
+// which the K interleaved directions exhaust.
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+__device__ __forceinline__ unsigned in_vgpr(unsigned x)
+{
+    unsigned v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
 
 __device__ __forceinline__ void lds_add(float *p, float v)
 {
@@ -62,10 +153,24 @@ __device__ __forceinline__ float lane_get(float v, int src)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
-// One segment of depth length ds in the lane's cell, for every bin.
+// Lane shift along b by one column (within each row of 8): row_shr:1 /
+// row_shl:1 of DPP move a value from the lane before / after; the lanes of
+// column 0 / 7, whose value comes from outside the row, are overwritten by
+// the caller.
+__device__ __forceinline__ float shift_prev(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float shift_next(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+}
+
+// One segment of depth length ds in the lane's cell, for every bin; fw[b] is
+// |n_a| / (kappa_b h) of the cell.
 template <int NB>
-__device__ __forceinline__ void segment(const v3f *F, float ds, float invw, float w, float *I,
-                                        float *a1, float *a2)
+__device__ __forceinline__ void segment(const v3f *F, const float *fw, float ds, float invw,
+                                        float *I, float *a1, float *a2)
 {
     const float dl = ds * invw;
 #pragma unroll
@@ -74,7 +179,7 @@ __device__ __forceinline__ void segment(const v3f *F, float ds, float invw, floa
         // large-x branch
         const float e = __builtin_amdgcn_exp2f(-x * ART_LOG2E);
         const float e1l = 1.0f - e;
-        const float lphil = e1l * (F[b].y * w);
+        const float lphil = e1l * fw[b];
         const float lpsil = ds - lphil;
         // small-x branch: q = (x - 1 + e^{-x}) / x^2
         const float qq = fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 720.0f, -1.0f / 120.0f),
@@ -93,24 +198,6 @@ __device__ __forceinline__ void segment(const v3f *F, float ds, float invw, floa
     }
 }
 
-// Lane shift along b by one column (within each row of 8): row_shr:1 /
-// row_shl:1 of DPP move a value from the lane before / after; the lanes of
-// column 0 / 7, whose value comes from outside the row, are overwritten by
-// the caller.
-__device__ __forceinline__ float shift_prev(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float shift_next(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
-}
-
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(4))) const v4u c_u4;
-typedef __attribute__((address_space(4))) const ArtDir c_dir;
-typedef __attribute__((address_space(4))) const int c_int;
-
 template <int NB, int K>
 __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restrict__ items,
                                                         const ArtMeshDesc *__restrict__ meshes,
@@ -119,7 +206,9 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     extern __shared__ __align__(16) float lds[];
     const ArtItem it = items[blockIdx.x];
     const ArtMeshDesc &M = meshes[it.mesh];
-    const int dbeg = M.bucket_start[it.bucket], dend = M.bucket_start[it.bucket + 1];
+    // (read through a generic pointer, which the compiler cannot prove uniform)
+    const int dbeg = __builtin_amdgcn_readfirstlane(M.bucket_start[it.bucket]);
+    const int dend = __builtin_amdgcn_readfirstlane(M.bucket_start[it.bucket + 1]);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -151,220 +240,199 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const int col = lane & 7, row = lane >> 3;
     const int gb = lo_b + col, gc = lo_c + row;
     const bool in_dom = gb < Nb && gc < Nc;
-    // What a lane does when all rays move one column (b) or row (c) forward
-    // (+1) or back (-1): its ray leaves the tile or the mesh (store the
-    // state), it takes the neighbour lane's ray, or it loads a ray arriving
-    // from the next tile (otherwise a fresh ray enters the mesh with I_bc).
-    const bool lbp = col == 7 || gb + 1 >= Nb, tbp = col >= 1, ibp = col == 0 && gb >= 1;
-    const bool lbm = col == 0, tbm = col <= 6 && gb + 1 < Nb, ibm = col == 7 && gb + 1 < Nb;
-    const bool lcp = row == 7 || gc + 1 >= Nc, tcp = row >= 1, icp = row == 0 && gc >= 1;
-    const bool lcm = row == 0, tcm = row <= 6 && gc + 1 < Nc, icm = row == 7 && gc + 1 < Nc;
+    // All directions of the bucket share its octant, so along b the rays only
+    // ever move one way (sgb = +1 or -1, towards larger or smaller b), and so
+    // along c.  When all rays move one column (b) or row (c): the lane's ray
+    // leaves the tile or the mesh (store its state: Lb / Lc), the lane takes
+    // the neighbour lane's ray (Tb / Tc), or it loads a ray arriving from the
+    // next tile (Nb / Nc; otherwise a fresh ray enters the mesh with I_bc).
+    const bool bneg = (oct >> ab) & 1, cneg = (oct >> ac) & 1;
+    const bool Lb = in_dom && (bneg ? col == 0 : (col == 7 || gb + 1 >= Nb));
+    const bool Tb = bneg ? (col <= 6 && gb + 1 < Nb) : col >= 1;
+    const bool Nb_ = in_dom && (bneg ? (col == 7 && gb + 1 < Nb) : (col == 0 && gb >= 1));
+    const bool Lc = in_dom && (cneg ? row == 0 : (row == 7 || gc + 1 >= Nc));
+    const bool Tc = cneg ? (row <= 6 && gc + 1 < Nc) : row >= 1;
+    const bool Nc_ = in_dom && (cneg ? (row == 7 && gc + 1 < Nc) : (row == 0 && gc >= 1));
+    const int csrc = (min(7, max(0, row + (cneg ? 1 : -1))) << 3) + col;   // lane a c-move takes from
 
+    // LDS accumulators: per cell of the block, {A1, A2} of every bin.
     const int V = depth * 64;                             // cells of one block
     float *accl = lds;
     for (int i = threadIdx.x; i < NB * 2 * V; i += blockDim.x) accl[i] = 0.0f;
     __syncthreads();
 
-    g_f3 *fields = (g_f3 *)M.fields;
-    g_f *state = (g_f *)M.state;
-    c_u4 *geo = (c_u4 *)M.geo;
+    // Field records of the block: base at its lowest cell, lane offset fixed,
+    // slab offset in the scalar offset.
+    const long long base_cell = (long long)lo_a * sa + (long long)lo_b * sb + (long long)lo_c * sc;
+    const long long rec_left = (M.ncell - base_cell) * NB * 16;
+    const rsrc_t rF = make_rsrc((const float4 *)M.fields + base_cell * NB,
+                                (unsigned)min(rec_left, 0x7fffffffll));
+    const unsigned foff = in_dom ? (unsigned)((col * sb + row * sc) * NB * 16) : 0u;
+    auto slab_soff = [&](int t) {     // byte offset of the t-th slab swept
+        const int la = sig_neg ? nslab - 1 - t : t;
+        return (unsigned)(la * sa * NB * 16);
+    };
+    g_u4 *geo = (g_u4 *)M.geo;
     c_dir *dirs = (c_dir *)M.dirs;
     c_int *order = (c_int *)M.order;
     const int gstride = M.geo_stride;
-    const float I_bc = M.I_bc;
-    const long long xa0 = sig_neg ? Na - 1 - d0 : d0;
-    const long long cell0 = xa0 * sa + gb * sb + gc * sc;
-    const long long dcell = sig_neg ? -sa : sa;
+    // The bucket's ray states are one contiguous range (boundary slot of its
+    // first direction up to the last ray of its last direction).
+    const long long sbase = dirs[order[dbeg]].state_off - NB;
+    const c_dir &Dl = dirs[order[dend - 1]];
+    const rsrc_t rS = make_rsrc(M.state + sbase,
+                                (unsigned)((Dl.state_off + (long long)Dl.nj * Dl.nk * NB - sbase) * 4));
     unsigned int sseg = 0;   // segments of positive length per in-mesh lane (wave-uniform)
 
-    // A wave marches K directions of the bucket together: q0 + m * nwave, m < K.
-    // Software pipeline: at the top of slab t every load slab t+1 needs is
-    // issued (its fields, the rays that enter the tile during it, and the
-    // crossing table of slab t+2); they land while slab t is marched and are
-    // rotated into place at its end.  All of these loads are issued by every
-    // lane from a valid address (lanes that need no value read the
-    // direction's first state slot or cell 0): a load under a branch, or a
-    // dead register of a vector load, makes the compiler wait for it at once.
     for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
         bool act[K];
-        int dix[K], njm[K];
-        long long cur[K];       // state slot of the lane's current ray
-        long long soff[K];      // first state slot of the direction
+        int gbase[K];
+        unsigned cstride[K];    // bytes between rays of neighbouring c (nj slots)
+        unsigned dbase[K];      // byte offset of the direction's boundary slot in rS
+        unsigned cur[K];        // byte offset of the lane's current ray in rS
         float invw[K], wdir[K];
         float I[K][NB];
         float ib[K][NB], ic[K][NB];   // rays entering the tile during the current slab
-        bool needb[K], needc[K];
-        v4u gA[K], gB[K];             // crossing tables of the current and the next slab
-        // Rays entering the tile during the slab with crossing table g, for a
-        // lane whose ray is in slot `at` at the top of that slab.
-        auto load_incoming = [&](int m, const v4u &g, long long at, float *jb, float *jc,
-                                 bool &nbm, bool &ncm) {
-            const unsigned code = g.w;
-            const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
-            const bool b_first = (code >> 4) & 1u;
-            const long long dB = (long long)shb * NB;
-            const long long dC = (long long)shc * njm[m] * NB;
-            nbm = shb && in_dom && (shb > 0 ? ibp : ibm);
-            ncm = shc && in_dom && (shc > 0 ? icp : icm);
-            const long long slb = nbm ? at - (b_first ? 0 : dC) - dB : soff[m];
-            const long long slc = ncm ? at - (b_first ? dB : 0) - dC : soff[m];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                jb[b] = state[slb + b];
-                jc[b] = state[slc + b];
-            }
-        };
+        u32x4 gcur[K], gnext[K];      // crossing table entries of the current and next slab
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             const int q = q0 + m * nwave;
             act[m] = q < dend;
-            dix[m] = act[m] ? order[q] : order[q0];
-            const c_dir &D = dirs[dix[m]];
+            const int d = act[m] ? order[q] : order[q0];
+            const c_dir &D = dirs[d];
             const double tb = ab == 0 ? D.beta[0] : D.beta[1];
             const double tc = ac == 1 ? D.beta[1] : D.beta[2];
             const int Bb = (int)floor(fma(tb, (double)d0, 0.5));
             const int Bc = (int)floor(fma(tc, (double)d0, 0.5));
-            njm[m] = D.nj;
-            soff[m] = D.state_off;
-            cur[m] = D.state_off + ((long long)(gc - Bc - D.k0) * D.nj + (gb - Bb - D.j0)) * NB;
-            invw[m] = (float)D.invw;
-            wdir[m] = (float)D.w;
+            gbase[m] = d * gstride;
+            const unsigned db = (unsigned)((D.state_off - NB - sbase) * 4);
+            cur[m] = db + (unsigned)((1 + (gc - Bc - D.k0) * D.nj + (gb - Bb - D.j0)) * NB * 4);
+            cstride[m] = in_vgpr((unsigned)(D.nj * NB * 4));
+            dbase[m] = in_vgpr(db);
+            invw[m] = in_vgpr((float)D.invw);
+            wdir[m] = in_vgpr((float)D.w);
             // rays entering through the top face come from the block above
-            const bool from_above = in_dom && d0 > 0;
-            const long long s0 = from_above ? cur[m] : soff[m];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) I[m][b] = state[s0 + b];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) I[m][b] = from_above ? I[m][b] : I_bc;
-            const long long gbase = (long long)dix[m] * gstride;
-            gA[m] = geo[gbase + d0];
-            gB[m] = geo[gbase + min(d0 + 1, Na - 1)];
-            load_incoming(m, gA[m], cur[m], ib[m], ic[m], needb[m], needc[m]);
+            load_slot<NB>(rS, (in_dom && d0 > 0) ? cur[m] : dbase[m], I[m]);
+            gcur[m] = geo[gbase[m] + d0];
+            gnext[m] = geo[gbase[m] + min(d0 + 1, Na - 1)];
         }
-        // lanes outside the mesh read cell 0 (their results are never stored)
         v3f F[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) F[b] = fields[(in_dom ? cell0 : 0) * NB + b];
-        long long cell = cell0;
+        for (int b = 0; b < NB; ++b) F[b] = load_field(rF, foff + 16 * b, slab_soff(0));
 
         for (int t = 0; t < nslab; ++t) {
             const int i = d0 + t;
-            // prefetch for slab t+1 (past the last slab: harmless repeats)
-            const long long ncell = in_dom ? (t + 1 < nslab ? cell + dcell : cell) : 0;
+            // next slab's fields (past the last slab: a harmless repeat)
+            const unsigned so_next = slab_soff(t + 1 < nslab ? t + 1 : t);
             v3f Fn[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) Fn[b] = fields[ncell * NB + b];
-            float ibn[K][NB], icn[K][NB];
-            bool needbn[K], needcn[K];
-            v4u gC[K];
+            for (int b = 0; b < NB; ++b) Fn[b] = load_field(rF, foff + 16 * b, so_next);
+            // the table entry is the same in every lane: its code word goes to a
+            // scalar register, so that every branch on it is a scalar branch
+            unsigned codes[K];
+#pragma unroll
+            for (int m = 0; m < K; ++m) codes[m] = __builtin_amdgcn_readfirstlane(gcur[m].w);
+            // rays entering the tile during this slab; the table two slabs ahead
+            u32x4 gnext2[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const unsigned code = gA[m].w;
-                const long long at = cur[m] - (long long)((int)(code & 3u) - 1) * NB -
-                                     (long long)((int)((code >> 2) & 3u) - 1) * njm[m] * NB;
-                load_incoming(m, gB[m], at, ibn[m], icn[m], needbn[m], needcn[m]);
-                gC[m] = geo[(long long)dix[m] * gstride + min(i + 2, Na - 1)];
+                const unsigned code = codes[m];
+                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
+                const bool b_first = (code >> 4) & 1u;
+                const int dB = shb * NB * 4;
+                const int dC = shc * (int)cstride[m];
+                load_slot<NB>(rS, (shb && Nb_) ? cur[m] - (b_first ? 0 : dC) - dB : dbase[m], ib[m]);
+                load_slot<NB>(rS, (shc && Nc_) ? cur[m] - (b_first ? dB : 0) - dC : dbase[m], ic[m]);
+                gnext2[m] = geo[gbase[m] + min(i + 2, Na - 1)];
             }
+            float fw[K][NB];
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fw[m][b] = F[b].y * wdir[m];
             float a1[NB], a2[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) a1[b] = a2[b] = 0.0f;
 
+            // crossing of a b-plane: every ray moves from column gb to gb + shb
+            auto cross_b = [&](int m, int shb) {
+                store_slot<NB>(rS, Lb ? cur[m] : ART_OOB, I[m]);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float moved = bneg ? shift_next(I[m][b]) : shift_prev(I[m][b]);
+                    I[m][b] = Tb ? moved : ib[m][b];
+                }
+                cur[m] -= shb * NB * 4;
+            };
+            // crossing of a c-plane: every ray moves from row gc to gc + shc
+            auto cross_c = [&](int m, int shc) {
+                store_slot<NB>(rS, Lc ? cur[m] : ART_OOB, I[m]);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float moved = lane_get(I[m][b], csrc);
+                    I[m][b] = Tc ? moved : ic[m][b];
+                }
+                cur[m] -= shc * (int)cstride[m];
+            };
+
+            // phase 1: first segment of every direction
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m]) continue;
-                const v4u g = gA[m];
-                const unsigned code = g.w;
-                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
-                const bool b_first = (code >> 4) & 1u;
-                const float s1 = __uint_as_float(g.x), s2 = __uint_as_float(g.y),
-                            s3 = __uint_as_float(g.z);
-                sseg += code >> 5;
-                const long long dB = (long long)shb * NB;
-                const long long dC = (long long)shc * njm[m] * NB;
-                float *Im = I[m];
-                // crossing of a b-plane: every ray moves from column gb to gb + shb
-                auto cross_b = [&]() {
-                    if (in_dom && (shb > 0 ? lbp : lbm)) {
-#pragma unroll
-                        for (int b = 0; b < NB; ++b) state[cur[m] + b] = Im[b];
-                    }
-                    const bool take = shb > 0 ? tbp : tbm;
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const float moved = shb > 0 ? shift_prev(Im[b]) : shift_next(Im[b]);
-                        Im[b] = take ? moved : (needb[m] ? ib[m][b] : I_bc);
-                    }
-                    cur[m] -= dB;
-                };
-                // crossing of a c-plane: every ray moves from row gc to gc + shc
-                auto cross_c = [&]() {
-                    if (in_dom && (shc > 0 ? lcp : lcm)) {
-#pragma unroll
-                        for (int b = 0; b < NB; ++b) state[cur[m] + b] = Im[b];
-                    }
-                    const bool take = shc > 0 ? tcp : tcm;
-                    const int src = (min(7, max(0, row - shc)) << 3) + col;
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const float moved = lane_get(Im[b], src);
-                        Im[b] = take ? moved : (needc[m] ? ic[m][b] : I_bc);
-                    }
-                    cur[m] -= dC;
-                };
-                segment<NB>(F, s1, invw[m], wdir[m], Im, a1, a2);
-                if (shb && shc) {
-                    if (b_first) cross_b(); else cross_c();
-                    segment<NB>(F, s2, invw[m], wdir[m], Im, a1, a2);
-                    if (b_first) cross_c(); else cross_b();
-                    segment<NB>(F, s3, invw[m], wdir[m], Im, a1, a2);
-                } else if (shb || shc) {
-                    if (shb) cross_b(); else cross_c();
-                    segment<NB>(F, s2, invw[m], wdir[m], Im, a1, a2);
-                }
+                sseg += codes[m] >> 5;
+                segment<NB>(F, fw[m], __uint_as_float(gcur[m].x), invw[m], I[m], a1, a2);
             }
+            // phase 2: first crossing and second segment
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const unsigned code = codes[m];
+                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
+                if (!act[m] || !(shb || shc)) continue;
+                const bool b_first = (code >> 4) & 1u;
+                if (shb && (b_first || !shc)) cross_b(m, shb); else cross_c(m, shc);
+                segment<NB>(F, fw[m], __uint_as_float(gcur[m].y), invw[m], I[m], a1, a2);
+            }
+            // phase 3: second crossing and third segment
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const unsigned code = codes[m];
+                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
+                if (!act[m] || !(shb && shc)) continue;
+                const bool b_first = (code >> 4) & 1u;
+                if (b_first) cross_c(m, shc); else cross_b(m, shb);
+                segment<NB>(F, fw[m], __uint_as_float(gcur[m].z), invw[m], I[m], a1, a2);
+            }
+
             if (in_dom) {
                 const int la = (sig_neg ? Na - 1 - i : i) - lo_a;
-                const int lc = la * 64 + lane;
+                float *cellacc = accl + (la * 64 + lane) * (2 * NB);
                 if (nwave == 1) {
                     // a single wave owns the block: plain read-modify-write
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        accl[(2 * b) * V + lc] += a1[b];
-                        accl[(2 * b + 1) * V + lc] += a2[b];
+                        cellacc[2 * b] += a1[b];
+                        cellacc[2 * b + 1] += a2[b];
                     }
                 } else {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        lds_add(&accl[(2 * b) * V + lc], a1[b]);
-                        lds_add(&accl[(2 * b + 1) * V + lc], a2[b]);
+                        lds_add(&cellacc[2 * b], a1[b]);
+                        lds_add(&cellacc[2 * b + 1], a2[b]);
                     }
                 }
             }
-            // rotate the pipeline
-            cell += dcell;
 #pragma unroll
             for (int b = 0; b < NB; ++b) F[b] = Fn[b];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                gA[m] = gB[m];
-                gB[m] = gC[m];
-                needb[m] = needbn[m];
-                needc[m] = needcn[m];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    ib[m][b] = ibn[m][b];
-                    ic[m][b] = icn[m][b];
-                }
+                gcur[m] = gnext[m];
+                gnext[m] = gnext2[m];
             }
         }
         // rays leave through the block's far face (into the next block or out of the mesh)
 #pragma unroll
-        for (int m = 0; m < K; ++m) {
-            if (act[m] && in_dom) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) state[cur[m] + b] = I[m][b];
-            }
-        }
+        for (int m = 0; m < K; ++m)
+            store_slot<NB>(rS, (act[m] && in_dom) ? cur[m] : ART_OOB, I[m]);
     }
 
     // workgroup total of marched segments of positive length (work accounting)
@@ -379,8 +447,8 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     // Flush: this workgroup is the only writer of its block in this bucket's copy.
     g_f *dst = (g_f *)M.acc + (long long)it.bucket * NB * 2 * M.ncell;
     for (int idx = threadIdx.x; idx < NB * 2 * V; idx += blockDim.x) {
-        const int comp = idx / V, rem = idx - comp * V;
-        const int la = rem >> 6, l = rem & 63;
+        const int comp = idx % (2 * NB), cl = idx / (2 * NB);
+        const int la = cl >> 6, l = cl & 63;
         const int cb = lo_b + (l & 7), cc = lo_c + (l >> 3);
         if (la >= nslab || cb >= Nb || cc >= Nc) continue;
         const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
