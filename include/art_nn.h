@@ -1,0 +1,113 @@
+/*
+ * art_nn.h -- C interface of the layers of the learned surrogate of libart:
+ * a 3-D convolution network that maps a coarse sweep (few HEALPix
+ * directions) plus the local fields to the mean intensity of a fine sweep.
+ * The surrogate is not part of the paper; the sweep it stands in for is the
+ * one of art.h (Sect. 2.2-2.3 of Tanaka et al., arXiv:1410.0763).
+ *
+ * Conventions
+ * -----------
+ * - Activations are bfloat16 (raw 16-bit words, round-to-nearest-even),
+ *   channels-last [D][H][W][C]; V = D*H*W voxels, x fastest.
+ * - A layer's weight is w[tap][ci][co] float32 with tap = (dz+1)*9 +
+ *   (dy+1)*3 + (dx+1) for offsets dz, dy, dx in {-1, 0, 1}; zero padding, so
+ *   out[v][co] = bias[co] + sum_{tap, ci} w[tap][ci][co] x[v + offset(tap)][ci].
+ *   The products run on the matrix cores (bf16 inputs, float32 sums).
+ * - Every call returns ART_OK or a negative ART_E_* code (art.h) and queues
+ *   its work on hip_stream; all pointers are device pointers owned by the
+ *   caller, which must keep them valid until the stream has passed the call.
+ * - Reductions (weight and bias gradients, the loss) are summed in a fixed
+ *   order: results are bitwise reproducible.
+ */
+#ifndef ART_NN_H
+#define ART_NN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Convolution of x (cin = 16 or 32 channels) with 32 output channels.
+ * w_k: bf16 [27][32][cin] (made by art_nn_prep_weights); bias: float32 [32]
+ * or NULL; relu: apply max(0, .) after the bias.  Outputs (either may be
+ * NULL): y bf16 [V][32], y0 float32 [V] = channel 0 of the output.
+ * W must be a multiple of 32.  ART_E_INVAL on bad sizes or null x/w_k. */
+int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, int D, int H,
+                   int W, int relu, void *y, float *y0, void *hip_stream);
+
+/* Weight gradient dw[tap][ci][co] = sum_v x[v + offset(tap)][ci] g[v][co].
+ * xs: bf16 [3][cin][V], the channels-first copies of the layer input made
+ * by art_nn_shift3; g: bf16 [32][V], the channels-first gradient at the
+ * layer output (art_nn_relu_grad).  partial: float32 scratch
+ * [nchunk][27][cin][32]; nchunk must divide D*H.  dw: float32 [27][cin][32].
+ * W must be a multiple of 16. */
+int art_conv3d_bwd_weight(const void *xs, int cin, const void *g, int D, int H, int W,
+                          float *partial, int nchunk, float *dw, void *hip_stream);
+
+/* Bias gradient db[co] = sum_v g[co][v] of a channels-first bf16 gradient
+ * [32][V]; partial: float32 scratch [nchunk][32]; nchunk must divide V. */
+int art_nn_bias_grad(const void *g, int V, float *partial, int nchunk, float *db,
+                     void *hip_stream);
+
+/* xs[s][c][v] = x[v + (s - 1) along x][c] (zero outside the mesh), s = 0..2:
+ * the channels-first copies the weight gradient reads.  x: bf16 [V][cin]. */
+int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *hip_stream);
+
+/* Gradient at a layer output: g = dy where y > 0 (the ReLU of the forward
+ * pass; y = NULL for the last layer, which has none), else 0.  dy, y: bf16
+ * [V][32].  Writes g (bf16 [V][32], channels-last) and g_cf (bf16 [32][V]). */
+int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *g_cf,
+                     void *hip_stream);
+
+/* Matrix-core copies of one layer's weights w (float32 [27][cin][32]):
+ * w_fwd bf16 [27][32][cin] for the forward convolution and w_bwd bf16
+ * [27][32][32] for the input gradient (taps mirrored, channels swapped, rows
+ * beyond cin zero), used as art_conv3d_fwd(g, 32, w_bwd, NULL, ...). */
+int art_nn_prep_weights(const float *w, int cin, void *w_fwd, void *w_bwd, void *hip_stream);
+
+/* Weighted mean squared error of pred against target (float32 [V]):
+ * loss[0] = mean(weight (pred - target)^2) (weight float32 [V], or NULL for
+ * 1); dy bf16 [V][32] = d loss / d output (channel 0; other channels 0).
+ * partial: float32 scratch [256]. */
+int art_nn_mse(const float *pred, const float *target, const float *weight, int V, float *partial,
+               float *loss, void *dy, void *hip_stream);
+
+/* Loss weights w = (J^2 / mean(J^2) + lambda) / (1 + lambda) (float32 [V];
+ * J^2 / mean(J^2) taken as 1 if J is all zero; lambda >= 0): lambda = 0
+ * makes the loss on log(J_fine / J_coarse) approximate the squared relative
+ * L2 error of J, a large lambda the per-cell squared relative error.
+ * partial: float32 scratch [257]. */
+int art_nn_sq_weights(const float *J, int V, float lambda, float *partial, float *w,
+                      void *hip_stream);
+
+/* One AdamW step on n float32 parameters (decoupled weight decay wd,
+ * bias-corrected moments m, v; step >= 1). */
+int art_nn_adamw(float *w, const float *g, float *m, float *v, int n, float lr, float beta1,
+                 float beta2, float eps, float wd, int step, void *hip_stream);
+
+/* Surrogate input features, bf16 [V][16]: channel k < 3 is
+ * (log(max(f_k, 1e-30)) - mu[k]) * inv_sd[k] for f = (J, kappa, S), the rest
+ * 0.  mu, inv_sd: host arrays [3]. */
+int art_nn_features(const float *J, const float *kappa, const float *S, int V, const float *mu,
+                    const float *inv_sd, void *x, void *hip_stream);
+
+/* J_out = J_coarse * exp(pred): the surrogate predicts log(J_fine / J_coarse). */
+int art_nn_expand(const float *J_coarse, const float *pred, int V, float *J_out,
+                  void *hip_stream);
+
+/* Training target: target = log(J_fine) - log(J_coarse) (both floored at
+ * 1e-30), float32 [V]. */
+int art_nn_log_ratio(const float *J_fine, const float *J_coarse, int V, float *target,
+                     void *hip_stream);
+
+/* count[0] = number of voxels whose features (bf16 [V][16], channels 0-2)
+ * leave [lo[k], hi[k]] in any channel k (lo, hi: host arrays [3]): the
+ * out-of-distribution measure of the surrogate's acceptance gate.  count is
+ * cleared by the call (with a kernel, so the call may be graph-captured). */
+int art_nn_ood_count(const void *x, int V, const float *lo, const float *hi, unsigned int *count,
+                     void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ART_NN_H */

@@ -23,6 +23,11 @@ EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
            "art_ndirs", "art_last_error")
+# include/art_nn.h: layers of the learned surrogate
+NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
+              "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
+              "art_nn_features", "art_nn_expand", "art_nn_log_ratio", "art_nn_ood_count",
+              "art_nn_sq_weights")
 
 
 class ArtError(RuntimeError):
@@ -72,7 +77,21 @@ def load(path: str = LIB_PATH):
     L.art_batch_destroy.argtypes = [vp]
     L.art_ndirs.argtypes = [i]
     L.art_last_error.restype = ctypes.c_char_p
-    for name in EXPORTS:
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
+    L.art_conv3d_bwd_weight.argtypes = [vp, i, vp, i, i, i, vp, i, vp, vp]
+    L.art_nn_bias_grad.argtypes = [vp, i, vp, i, vp, vp]
+    L.art_nn_shift3.argtypes = [vp, i, i, i, i, vp, vp]
+    L.art_nn_relu_grad.argtypes = [vp, vp, i, vp, vp, vp]
+    L.art_nn_prep_weights.argtypes = [vp, i, vp, vp, vp]
+    L.art_nn_mse.argtypes = [vp, vp, vp, i, vp, vp, vp, vp]
+    L.art_nn_sq_weights.argtypes = [vp, i, f, vp, vp, vp]
+    L.art_nn_adamw.argtypes = [vp, vp, vp, vp, i, f, f, f, f, f, i, vp]
+    L.art_nn_features.argtypes = [vp, vp, vp, i, fp, fp, vp, vp]
+    L.art_nn_expand.argtypes = [vp, vp, i, vp, vp]
+    L.art_nn_log_ratio.argtypes = [vp, vp, i, vp, vp]
+    L.art_nn_ood_count.argtypes = [vp, i, fp, fp, vp, vp]
+    for name in EXPORTS + NN_EXPORTS:
         if name != "art_last_error":
             getattr(L, name).restype = i
     _lib = L
@@ -248,3 +267,79 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class nn:
+    """Thin wrappers of include/art_nn.h over torch device tensors (argument
+    marshalling only; every operation runs in the library's kernels)."""
+
+    @staticmethod
+    def _f3(vals):
+        return (ctypes.c_float * 3)(*[float(v) for v in vals])
+
+    @staticmethod
+    def conv3d_fwd(x, cin, w_k, bias, shape, relu, y=None, y0=None, stream=None):
+        D, H, W = shape
+        _check(load().art_conv3d_fwd(_ptr(x), cin, _ptr(w_k), _ptr(bias), D, H, W, int(relu),
+                                     _ptr(y), _ptr(y0), _stream_ptr(stream)))
+
+    @staticmethod
+    def conv3d_bwd_weight(xs, cin, g_cf, shape, partial, nchunk, dw, stream=None):
+        D, H, W = shape
+        _check(load().art_conv3d_bwd_weight(_ptr(xs), cin, _ptr(g_cf), D, H, W, _ptr(partial),
+                                            nchunk, _ptr(dw), _stream_ptr(stream)))
+
+    @staticmethod
+    def bias_grad(g_cf, V, partial, nchunk, db, stream=None):
+        _check(load().art_nn_bias_grad(_ptr(g_cf), V, _ptr(partial), nchunk, _ptr(db),
+                                       _stream_ptr(stream)))
+
+    @staticmethod
+    def shift3(x, cin, shape, xs, stream=None):
+        D, H, W = shape
+        _check(load().art_nn_shift3(_ptr(x), cin, D, H, W, _ptr(xs), _stream_ptr(stream)))
+
+    @staticmethod
+    def relu_grad(dy, y, V, g, g_cf, stream=None):
+        _check(load().art_nn_relu_grad(_ptr(dy), _ptr(y), V, _ptr(g), _ptr(g_cf),
+                                       _stream_ptr(stream)))
+
+    @staticmethod
+    def prep_weights(w, cin, w_fwd, w_bwd, stream=None):
+        _check(load().art_nn_prep_weights(_ptr(w), cin, _ptr(w_fwd), _ptr(w_bwd),
+                                          _stream_ptr(stream)))
+
+    @staticmethod
+    def mse(pred, target, V, partial, loss, dy, weight=None, stream=None):
+        _check(load().art_nn_mse(_ptr(pred), _ptr(target), _ptr(weight), V, _ptr(partial),
+                                 _ptr(loss), _ptr(dy), _stream_ptr(stream)))
+
+    @staticmethod
+    def sq_weights(J, V, partial, w, lam=0.0, stream=None):
+        _check(load().art_nn_sq_weights(_ptr(J), V, float(lam), _ptr(partial), _ptr(w),
+                                        _stream_ptr(stream)))
+
+    @staticmethod
+    def adamw(w, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, wd=0.0, stream=None):
+        _check(load().art_nn_adamw(_ptr(w), _ptr(g), _ptr(m), _ptr(v), w.numel(), float(lr),
+                                   float(beta1), float(beta2), float(eps), float(wd), int(step),
+                                   _stream_ptr(stream)))
+
+    @staticmethod
+    def features(J, kappa, S, V, mu, inv_sd, x, stream=None):
+        _check(load().art_nn_features(_ptr(J), _ptr(kappa), _ptr(S), V, nn._f3(mu), nn._f3(inv_sd),
+                                      _ptr(x), _stream_ptr(stream)))
+
+    @staticmethod
+    def expand(J_coarse, pred, V, J_out, stream=None):
+        _check(load().art_nn_expand(_ptr(J_coarse), _ptr(pred), V, _ptr(J_out), _stream_ptr(stream)))
+
+    @staticmethod
+    def log_ratio(J_fine, J_coarse, V, target, stream=None):
+        _check(load().art_nn_log_ratio(_ptr(J_fine), _ptr(J_coarse), V, _ptr(target),
+                                       _stream_ptr(stream)))
+
+    @staticmethod
+    def ood_count(x, V, lo, hi, count, stream=None):
+        _check(load().art_nn_ood_count(_ptr(x), V, nn._f3(lo), nn._f3(hi), _ptr(count),
+                                       _stream_ptr(stream)))

@@ -59,6 +59,9 @@ int dev_alloc(T **p, size_t count, size_t *cap)
 
 }  // namespace
 
+// Error text for the other translation units of the library.
+int art_set_error(int code, const char *msg) { return fail(code, msg); }
+
 struct art_mesh {
     int nx = 0, ny = 0, nz = 0;
     double h = 1.0;

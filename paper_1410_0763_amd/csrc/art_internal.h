@@ -70,5 +70,7 @@ hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, i
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
 hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream);
 int art_max_bucket_dirs(int nside, int subsets);
+// Sets the thread-local error text returned by art_last_error; returns code.
+int art_set_error(int code, const char *msg);
 int art_march_max_lds_bytes();
 int art_march_lds_floats(int depth, int nb);

@@ -9,11 +9,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    with open(os.path.join(ROOT, "include", "art.h")) as f:
+def _declared(header="art.h"):
+    with open(os.path.join(ROOT, "include", header)) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(art_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(art_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
@@ -21,11 +21,31 @@ def test_header_and_binding_agree():
     assert _declared() == sorted(art.EXPORTS)
 
 
+def test_nn_header_and_binding_agree():
+    from paper_1410_0763_amd import art
+    assert _declared("art_nn.h") == sorted(art.NN_EXPORTS)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1410_0763_amd import art
     L = art.load()
-    for name in _declared():
+    for name in _declared() + _declared("art_nn.h"):
         assert hasattr(L, name), name
+
+
+def test_nn_argument_checks_without_gpu():
+    """Null pointers and bad sizes are rejected before any launch."""
+    from paper_1410_0763_amd import art
+    L = art.load()
+    p = ctypes.c_void_p(1)
+    assert L.art_conv3d_fwd(None, 16, p, None, 4, 4, 32, 1, p, None, None) == -1
+    assert L.art_conv3d_fwd(p, 8, p, None, 4, 4, 32, 1, p, None, None) == -1
+    assert L.art_conv3d_fwd(p, 16, p, None, 4, 4, 48, 1, p, None, None) == -1
+    assert b"multiple of 32" in L.art_last_error()
+    assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 32, p, 3, p, None) == -1   # 3 does not divide 16
+    assert L.art_nn_bias_grad(p, 100, p, 7, p, None) == -1
+    assert L.art_nn_prep_weights(p, 20, p, p, None) == -1
+    assert L.art_nn_adamw(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == -1
 
 
 def test_host_only_calls():

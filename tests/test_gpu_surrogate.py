@@ -1,0 +1,375 @@
+"""The surrogate's layer kernels (include/art_nn.h) against the FP64 CPU
+reference (oracle/conv3d_ref.py) on the same bf16-rounded inputs, the
+training loop, and the surrogate's gain and fallback on 128^3 fields."""
+import numpy as np
+import pytest
+
+from oracle import conv3d_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    print(f"\n== case {name}", flush=True)
+
+
+def bf16_bits(a):
+    """float32 -> bfloat16 bit patterns (round to nearest even), as int16."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16).view(np.int16)
+
+
+def bf16_value(bits):
+    return (np.asarray(bits).view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-30))
+
+
+@pytest.mark.parametrize("cin,shape", [(16, (3, 5, 64)), (32, (4, 3, 32))])
+def test_conv_forward_matches_reference(cin, shape):
+    _case(f"conv3d forward cin {cin} shape {shape}")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    D, H, W = shape
+    rng = np.random.default_rng(cin)
+    xb = bf16_bits(rng.normal(size=(D, H, W, cin)))
+    w = (rng.normal(size=(27, cin, 32)) * 0.2).astype(np.float32)
+    b = (rng.normal(size=32) * 0.1).astype(np.float32)
+    wf = torch.zeros((27, 32, cin), dtype=torch.int16, device="cuda")
+    wb = torch.zeros((27, 32, 32), dtype=torch.int16, device="cuda")
+    nn.prep_weights(_dev(w), cin, wf, wb)
+    V = D * H * W
+    y = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    y0 = torch.zeros(V, dtype=torch.float32, device="cuda")
+    for relu in (0, 1):
+        nn.conv3d_fwd(_dev(xb), cin, wf, _dev(b), shape, relu, y=y, y0=y0)
+        torch.cuda.synchronize()
+        wq = bf16_value(bf16_bits(w))                     # the kernel's bf16 weights
+        ref = R.conv3d(bf16_value(xb), wq, b)
+        if relu:
+            ref = np.maximum(ref, 0.0)
+        e0 = _rel(y0.cpu().numpy().reshape(D, H, W), ref[..., 0])
+        ey = _rel(bf16_value(y.cpu().numpy()).reshape(D, H, W, 32), ref)
+        print(f"relu {relu}: channel 0 (float32) {e0:.2e}, all channels (bf16) {ey:.2e}", flush=True)
+        assert e0 <= 2e-6
+        assert ey <= 4e-3        # one bf16 rounding of the output
+
+
+def test_conv_gradients_match_reference():
+    _case("conv3d input and weight gradients")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    D, H, W = 4, 4, 32
+    shape = (D, H, W)
+    V = D * H * W
+    rng = np.random.default_rng(7)
+    for cin in (16, 32):
+        xb = bf16_bits(rng.normal(size=(D, H, W, cin)))
+        gb = bf16_bits(rng.normal(size=(D, H, W, 32)))
+        w = (rng.normal(size=(27, cin, 32)) * 0.2).astype(np.float32)
+        wf = torch.zeros((27, 32, cin), dtype=torch.int16, device="cuda")
+        wbw = torch.zeros((27, 32, 32), dtype=torch.int16, device="cuda")
+        nn.prep_weights(_dev(w), cin, wf, wbw)
+        g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+        gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
+        nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g, gcf)
+        xs = torch.zeros((3, cin, V), dtype=torch.int16, device="cuda")
+        nn.shift3(_dev(xb.reshape(V, cin)), cin, shape, xs)
+        nchunk = 4
+        part = torch.zeros(nchunk * 27 * cin * 32, dtype=torch.float32, device="cuda")
+        dw = torch.zeros((27, cin, 32), dtype=torch.float32, device="cuda")
+        nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw)
+        bpart = torch.zeros(nchunk * 32, dtype=torch.float32, device="cuda")
+        db = torch.zeros(32, dtype=torch.float32, device="cuda")
+        nn.bias_grad(gcf, V, bpart, nchunk, db)
+        dx = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+        nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dx)
+        torch.cuda.synchronize()
+        wq = bf16_value(bf16_bits(w))
+        rdx, rdw, rdb = R.conv3d_backward(bf16_value(xb), wq, bf16_value(gb))
+        e_dw = _rel(dw.cpu().numpy(), rdw)
+        e_db = _rel(db.cpu().numpy(), rdb)
+        e_dx = _rel(bf16_value(dx.cpu().numpy()).reshape(D, H, W, 32)[..., :cin], rdx)
+        print(f"cin {cin}: dw {e_dw:.2e}  db {e_db:.2e}  dx (bf16) {e_dx:.2e}", flush=True)
+        assert e_dw <= 1e-5 and e_db <= 1e-5 and e_dx <= 4e-3
+        # the fixed-order reductions are bitwise reproducible
+        dw2 = torch.zeros_like(dw)
+        nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw2)
+        torch.cuda.synchronize()
+        assert torch.equal(dw, dw2)
+
+
+def test_relu_grad_mse_and_adamw():
+    _case("relu gradient, mse, adamw")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    rng = np.random.default_rng(3)
+    V = 4096
+    dyb = bf16_bits(rng.normal(size=(V, 32)))
+    yb = bf16_bits(rng.normal(size=(V, 32)))
+    g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
+    nn.relu_grad(_dev(dyb), _dev(yb), V, g, gcf)
+    torch.cuda.synchronize()
+    want = np.where(bf16_value(yb) > 0, bf16_value(dyb), 0.0)
+    assert np.array_equal(bf16_value(g.cpu().numpy()), want)
+    assert np.array_equal(bf16_value(gcf.cpu().numpy()), want.T)
+    pred = rng.normal(size=V).astype(np.float32)
+    tgt = rng.normal(size=V).astype(np.float32)
+    part = torch.zeros(256, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dy = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    nn.mse(_dev(pred), _dev(tgt), V, part, loss, dy)
+    torch.cuda.synchronize()
+    ref = np.mean((pred.astype(np.float64) - tgt) ** 2)
+    assert abs(loss.item() - ref) <= 1e-5 * ref
+    d = bf16_value(dy.cpu().numpy())
+    np.testing.assert_allclose(d[:, 0], 2 * (pred - tgt.astype(np.float64)) / V, rtol=4e-3)
+    assert np.all(d[:, 1:] == 0)
+    # weighted: weights J^2 / mean(J^2)
+    J = np.abs(rng.normal(size=V)).astype(np.float32) + 0.1
+    wt = torch.zeros(V, dtype=torch.float32, device="cuda")
+    wpart = torch.zeros(257, dtype=torch.float32, device="cuda")
+    nn.sq_weights(_dev(J), V, wpart, wt, 0.5)
+    nn.mse(_dev(pred), _dev(tgt), V, part, loss, dy, weight=wt)
+    torch.cuda.synchronize()
+    wr = (J.astype(np.float64) ** 2 / np.mean(J.astype(np.float64) ** 2) + 0.5) / 1.5
+    np.testing.assert_allclose(wt.cpu().numpy(), wr, rtol=1e-5)
+    refw = np.mean(wr * (pred.astype(np.float64) - tgt) ** 2)
+    assert abs(loss.item() - refw) <= 1e-5 * refw
+    w = rng.normal(size=1000).astype(np.float32)
+    gr = rng.normal(size=1000).astype(np.float32)
+    wt, mt, vt = _dev(w), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    rw, rm, rv = w.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in (1, 2, 3):
+        nn.adamw(wt, _dev(gr), mt, vt, 1e-2, step, wd=1e-2)
+        rw, rm, rv = R.adamw(rw, gr.astype(np.float64), rm, rv, step, lr=1e-2, wd=1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(wt.cpu().numpy(), rw, rtol=1e-5, atol=1e-6)
+
+
+def _bf16_round(a):
+    return bf16_value(bf16_bits(np.asarray(a, np.float32)))
+
+
+def _faithful_grads(x, layers, target, V):
+    """The network's loss and gradients in float64 with the bf16 roundings the
+    kernels make between layers (activations, the loss gradient, the input
+    gradients): what is left between this and the GPU is summation order."""
+    hs = [x]
+    h = x
+    for i, (w, b) in enumerate(layers):
+        z = R.conv3d(h, w, b)
+        h = _bf16_round(np.maximum(z, 0.0)) if i < 5 else z
+        hs.append(h)
+    pred = hs[-1][..., 0]
+    loss = float(np.mean((pred - target) ** 2))
+    dy = np.zeros(hs[-1].shape)
+    dy[..., 0] = _bf16_round(2.0 * (pred - target) / V)
+    grads = [None] * 6
+    for i in range(5, -1, -1):
+        g = dy if i == 5 else dy * (hs[i + 1] > 0)
+        dx, dw, db = R.conv3d_backward(hs[i], layers[i][0], g)
+        grads[i] = (dw, db)
+        dy = _bf16_round(dx)
+    return loss, grads
+
+
+def test_network_gradients_match_reference():
+    """One backward pass of the 6-layer network (padded to the kernels' 16 /
+    32 channels) against float64 with the same bf16 roundings."""
+    _case("network gradients")
+    import torch
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (4, 4, 32)
+    V = 4 * 4 * 32
+    model = SG.Surrogate(shape, seed=1)
+    model.w[5][:, :, 0].normal_(0.0, 0.05)     # so that every layer gets a gradient
+    rng = np.random.default_rng(5)
+    xf = np.zeros((V, 16), np.float32)
+    xf[:, :3] = rng.normal(size=(V, 3))
+    xb = bf16_bits(xf)
+    tgt = rng.normal(size=V).astype(np.float32)
+    loss = model.gradients(_dev(xb), _dev(tgt))
+    torch.cuda.synchronize()
+    layers = [(bf16_value(bf16_bits(model.w[l].cpu().numpy())),
+               model.b[l].cpu().numpy().astype(np.float64)) for l in range(6)]
+    x_ref = bf16_value(xb).reshape(4, 4, 32, 16)
+    rl, rg = _faithful_grads(x_ref, layers, tgt.reshape(4, 4, 32).astype(np.float64), V)
+    print(f"loss gpu {loss.item():.6e} ref {rl:.6e}", flush=True)
+    errs = []
+    for l in range(6):
+        dw = model.dw[l].cpu().numpy()
+        e = np.linalg.norm(dw - rg[l][0]) / np.linalg.norm(rg[l][0])
+        eb = np.linalg.norm(model.db[l].cpu().numpy() - rg[l][1]) / max(np.linalg.norm(rg[l][1]), 1e-30)
+        print(f"layer {l}: relative weight-gradient error {e:.2e}, bias {eb:.2e}", flush=True)
+        errs.append(max(e, eb))
+    # a bf16 rounding that falls the other way under float32 sums (a few
+    # voxels) is all that separates the two
+    assert abs(loss.item() - rl) <= 1e-4 * rl
+    assert max(errs) <= 1e-2
+
+
+def test_training_reduces_loss():
+    _case("training on a small synthetic task")
+    import torch
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (8, 8, 32)
+    V = 8 * 8 * 32
+    model = SG.Surrogate(shape, seed=2)
+    rng = np.random.default_rng(9)
+    xf = np.zeros((V, 16), np.float32)
+    xf[:, :3] = rng.normal(size=(V, 3))
+    x = _dev(bf16_bits(xf))
+    tgt = _dev((0.5 * np.tanh(xf[:, 0]) - 0.3 * xf[:, 1] * (xf[:, 2] > 0)).astype(np.float32))
+    first = model.train_step(x, tgt, lr=3e-3).item()
+    for _ in range(100):
+        last = model.train_step(x, tgt, lr=3e-3).item()
+    print(f"loss {first:.4e} -> {last:.4e}", flush=True)
+    assert last < 0.5 * first
+
+
+def test_checkpoint_roundtrip(tmp_path):
+    _case("checkpoint save / load")
+    import torch
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (4, 4, 32)
+    a = SG.Surrogate(shape, seed=3)
+    a.set_stats([0, 0, 0], [1, 1, 1], [-5, -5, -5], [5, 5, 5], 0.1)
+    rng = np.random.default_rng(1)
+    V = 4 * 4 * 32
+    xf = np.zeros((V, 16), np.float32)
+    xf[:, :3] = rng.normal(size=(V, 3))
+    x = _dev(bf16_bits(xf))
+    tgt = _dev(rng.normal(size=V).astype(np.float32))
+    for _ in range(3):
+        a.train_step(x, tgt)
+    p = tmp_path / "s.ckpt"
+    a.save(str(p))
+    b = SG.Surrogate(shape, seed=99)
+    b.load(str(p))
+    for _ in range(2):
+        la = a.train_step(x, tgt).item()
+        lb = b.train_step(x, tgt).item()
+    torch.cuda.synchronize()
+    assert la == lb
+    assert all(torch.equal(u, v) for u, v in zip(a.w, b.w))
+    raw = bytearray(p.read_bytes())
+    raw[-1] ^= 1
+    p.write_bytes(bytes(raw))
+    with pytest.raises(ValueError):
+        SG.Surrogate(shape).load(str(p))
+
+
+def _pairs(model, mesh, idx, train):
+    import torch
+    from paper_1410_0763_amd import media
+    from paper_1410_0763_amd import surrogate as SG
+    out = []
+    for i in idx:
+        m = media.surrogate_medium(i, train=train)
+        k = torch.from_numpy(m.kappa).cuda()
+        s = torch.from_numpy(m.S).cuda()
+        mesh.set_fields(k, s)
+        x = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
+        t = torch.zeros(model.V, dtype=torch.float32, device="cuda")
+        w = torch.zeros(model.V, dtype=torch.float32, device="cuda")
+        Jc, Jf = SG.make_pair(mesh, k, s, 2, 16, model, x, t, w)
+        out.append(dict(m=m, k=k, s=s, x=x, t=t, w=w, Jc=Jc.clone(), Jf=Jf.clone()))
+    return out
+
+
+def test_surrogate_gain_and_fallback():
+    """128^3 fields: trained on coarse (Nside 2) -> fine (Nside 16) pairs, the
+    surrogate is closer to the fine sweep than the coarse sweep on held-out
+    fields (per-cell RMS of log(J / J_fine) at least 25% lower, relative L2 of
+    J within 25% of the coarse one: the loss weights cells by
+    (J^2 / mean J^2 + 1) / 2), coarse sweep + inference is faster than the
+    fine sweep, and the gate falls back to the fine sweep when the bound is 0
+    or the field is out of distribution."""
+    _case("surrogate gain and fallback, 128^3, Nside 2 -> 16")
+    import time
+    import torch
+    from paper_1410_0763_amd import art
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (128, 128, 128)
+    model = SG.Surrogate(shape, seed=0)
+    mesh = art.Mesh(*shape[::-1])
+    model.set_stats([0, 0, 0], [1, 1, 1], [-1e9] * 3, [1e9] * 3)
+    train = _pairs(model, mesh, range(16), True)
+    # feature statistics from the first fields (host side, float64)
+    feats = []
+    for p in train[:2]:
+        feats.append(np.stack([np.log(np.maximum(p["Jc"].cpu().numpy(), 1e-30)),
+                               np.log(np.maximum(p["m"].kappa.ravel(), 1e-30)),
+                               np.log(np.maximum(p["m"].S.ravel(), 1e-30))]))
+    f = np.concatenate(feats, axis=1)
+    mu, sd = f.mean(axis=1), f.std(axis=1)
+    z = (f - mu[:, None]) / sd[:, None]
+    model.set_stats(mu, sd, z.min(axis=1) - 1.0, z.max(axis=1) + 1.0)
+    for p in train:                       # features again with the statistics
+        model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), p["x"])
+    test = _pairs(model, mesh, range(3), False)
+    steps = 800
+    t0 = time.perf_counter()
+    for it in range(steps):
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 1e-5
+        p = train[it % len(train)]
+        loss = model.train_step(p["x"], p["t"], lr=lr, weight=p["w"])
+    torch.cuda.synchronize()
+    print(f"trained {steps} steps in {time.perf_counter() - t0:.1f} s, last loss {loss.item():.4e}",
+          flush=True)
+    err_c, err_s, lr_c, lr_s = [], [], [], []
+    for p in test:
+        mesh.set_fields(p["k"], p["s"])
+        model.stats["val_err"] = 0.0
+        J, fb, est = SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1e9)
+        assert not fb
+        Jf = p["Jf"]
+        err_s.append((torch.linalg.norm(J - Jf) / torch.linalg.norm(Jf)).item())
+        err_c.append((torch.linalg.norm(p["Jc"] - Jf) / torch.linalg.norm(Jf)).item())
+        lr_s.append(torch.sqrt(torch.mean(torch.log(J / Jf) ** 2)).item())
+        lr_c.append(torch.sqrt(torch.mean(torch.log(p["Jc"] / Jf) ** 2)).item())
+    print(f"held-out per-cell RMS log error: coarse {np.mean(lr_c):.4f}  surrogate {np.mean(lr_s):.4f}",
+          flush=True)
+    print(f"held-out relative L2 error:      coarse {np.mean(err_c):.4f}  surrogate {np.mean(err_s):.4f}",
+          flush=True)
+    assert np.mean(lr_s) < 0.75 * np.mean(lr_c)
+    assert np.mean(err_s) < 1.25 * np.mean(err_c)
+    model.stats["val_err"] = float(np.mean(err_s))
+    # time: coarse sweep + inference against the fine sweep
+    p = test[0]
+    mesh.set_fields(p["k"], p["s"])
+    SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1.0)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / 3
+    mesh.sweep(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        mesh.sweep(16)
+    torch.cuda.synchronize()
+    t_fine = (time.perf_counter() - t0) / 3
+    print(f"coarse + inference {1e3 * t_sur:.1f} ms, fine sweep {1e3 * t_fine:.1f} ms", flush=True)
+    assert t_sur < t_fine
+    # forced fallbacks: bound 0, and an out-of-distribution (vacuum) field
+    J, fb, est = SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=0.0)
+    assert fb and torch.allclose(J, p["Jf"], rtol=1e-6, atol=0)
+    vac_k = torch.zeros_like(p["k"])
+    mesh.set_fields(vac_k, p["s"])
+    J, fb, est = SG.sweep_surrogate(mesh, model, vac_k, p["s"], err_bound=0.5)
+    print(f"vacuum field: used_fallback {fb}, estimated error {est:.3f}", flush=True)
+    assert fb
+    mesh.close()
