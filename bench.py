@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -133,6 +135,151 @@ def cpu_baseline(medium, d_range=(366, 402)):
                       f"4 bins ({units:.3e} segment-bin updates in {dt:.1f} s)"}
 
 
+def bench_batched(count=48, replays=5):
+    """The uneven batch (48 meshes, sides 32-128, Nside 2/4/8, 1-4 bins): one
+    graph replay of the batched form against the 48 plain sweeps it replaces
+    (each mesh at its default tuning), both timed with HIP events."""
+    import torch
+    from paper_1410_0763_amd import art, media
+    meds = media.batch_media(count=count)
+    meshes = []
+    for m in meds:
+        nb, nz, ny, nx = m.kappa.shape
+        mesh = art.Mesh(nx, ny, nz, m.cell_size)
+        mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        meshes.append(mesh)
+    outs = [mesh.alloc_outputs(m.nside) for mesh, m in zip(meshes, meds)]
+    for mesh, m, o in zip(meshes, meds, outs):          # warm-up (allocations, schedules)
+        mesh.sweep(m.nside, gamma_w=m.gamma_w, out=o)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for mesh, m, o in zip(meshes, meds, outs):
+        mesh.sweep(m.nside, gamma_w=m.gamma_w, out=o)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    batch = art.Batch(meshes, [m.nside for m in meds], [m.gamma_w for m in meds])
+    batch.launch()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(replays):
+        e0.record()
+        batch.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    st = batch.stats()
+    seg_bins = st["segment_bins"]
+    batch_ms = min(times)
+    rec = {"metric": "segment-bin updates/s of the batched form (48 uneven meshes, one graph replay)",
+           "value": seg_bins / (batch_ms / 1e3), "unit": "seg-bin updates/s",
+           "batch_ms": batch_ms, "plain_48_calls_ms": plain_ms,
+           "plain_value": seg_bins / (plain_ms / 1e3), "speedup_vs_plain": plain_ms / batch_ms,
+           "segment_bins": seg_bins, "meshes": count, "replays": replays,
+           "config": {"workload": "48 meshes, sides 32-128 (a third cubes), lognormal sigma_ln 1, "
+                                  "Nside 2/4/8, 1-4 bins, seeds 4000+i"}}
+    batch.close()
+    for mesh in meshes:
+        mesh.close()
+    print(json.dumps(rec), flush=True)
+
+
+def bench_surrogate(train_fields=16, steps=800):
+    """128^3, Nside 2 -> 16: time of coarse sweep + network inference against
+    the fine sweep, held-out errors, and the conv layer's matrix-core rate."""
+    import torch
+    from paper_1410_0763_amd import art, media
+    from paper_1410_0763_amd import surrogate as SG
+    from paper_1410_0763_amd.art import nn
+    shape = (128, 128, 128)
+    V = 128 ** 3
+    model = SG.Surrogate(shape, seed=0)
+    model.set_stats([0, 0, 0], [1, 1, 1], [-1e9] * 3, [1e9] * 3)
+    mesh = art.Mesh(*shape)
+
+    def pairs(idx, train):
+        out = []
+        for i in idx:
+            m = media.surrogate_medium(i, train=train)
+            k, s = torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda()
+            mesh.set_fields(k, s)
+            x = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
+            t = torch.zeros(V, dtype=torch.float32, device="cuda")
+            w = torch.zeros(V, dtype=torch.float32, device="cuda")
+            Jc, Jf = SG.make_pair(mesh, k, s, 2, 16, model, x, t, w)
+            out.append(dict(m=m, k=k, s=s, x=x, t=t, w=w, Jc=Jc.clone(), Jf=Jf.clone()))
+        return out
+    train = pairs(range(train_fields), True)
+    f = np.concatenate([np.stack([np.log(np.maximum(p["Jc"].cpu().numpy(), 1e-30)),
+                                  np.log(np.maximum(p["m"].kappa.ravel(), 1e-30)),
+                                  np.log(np.maximum(p["m"].S.ravel(), 1e-30))]) for p in train[:2]], 1)
+    mu, sd = f.mean(1), f.std(1)
+    z = (f - mu[:, None]) / sd[:, None]
+    model.set_stats(mu, sd, z.min(1) - 1.0, z.max(1) + 1.0)
+    for p in train:
+        model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), p["x"])
+    test = pairs(range(4), False)
+    t0 = time.perf_counter()
+    for it in range(steps):
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 1e-5
+        p = train[it % len(train)]
+        model.train_step(p["x"], p["t"], lr=lr, weight=p["w"])
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    lr_c, lr_s, l2_c, l2_s = [], [], [], []
+    model.stats["val_err"] = 0.0
+    for p in test:
+        mesh.set_fields(p["k"], p["s"])
+        J, fb, _ = SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1e9)
+        Jf = p["Jf"]
+        lr_s.append(torch.sqrt(torch.mean(torch.log(J / Jf) ** 2)).item())
+        lr_c.append(torch.sqrt(torch.mean(torch.log(p["Jc"] / Jf) ** 2)).item())
+        l2_s.append((torch.linalg.norm(J - Jf) / torch.linalg.norm(Jf)).item())
+        l2_c.append((torch.linalg.norm(p["Jc"] - Jf) / torch.linalg.norm(Jf)).item())
+    model.stats["val_err"] = float(np.mean(l2_s))
+    p = test[0]
+    mesh.set_fields(p["k"], p["s"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+    x = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
+    sur_ms = timed(lambda: SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1.0, x=x))
+    fine_ms = timed(lambda: mesh.sweep(16))
+    coarse_ms = timed(lambda: mesh.sweep(2))
+    model.forward(p["x"])
+    infer_ms = timed(lambda: model.forward(p["x"]))
+    # one 32 -> 32 channel layer (the network's dominant kernel)
+    y = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    conv_ms = timed(lambda: nn.conv3d_fwd(model.acts[0], 32, model.w_fwd[1], model.b[1], shape, 1, y=y), 20)
+    conv_flop = 2.0 * 27 * 32 * 32 * V
+    rec = {"metric": "surrogate: coarse sweep + inference time against the fine sweep (128^3, Nside 2 -> 16)",
+           "value": fine_ms / sur_ms, "unit": "x faster than the fine sweep",
+           "surrogate_ms": sur_ms, "fine_sweep_ms": fine_ms, "coarse_sweep_ms": coarse_ms,
+           "inference_ms": infer_ms, "train_steps": steps, "train_s": train_s,
+           "held_out_log_rms": {"coarse": float(np.mean(lr_c)), "surrogate": float(np.mean(lr_s))},
+           "held_out_rel_l2": {"coarse": float(np.mean(l2_c)), "surrogate": float(np.mean(l2_s))},
+           "params": model.n_params(),
+           "roofline": {"bound": "mfma", "kernel": "conv3d_fwd_kernel<32> (one 32->32 layer, 128^3)",
+                        "achieved": conv_flop / (conv_ms / 1e3) / 1e12, "peak": 2500.0,
+                        "unit": "TFLOP/s", "frac": conv_flop / (conv_ms / 1e3) / 1e12 / 2500.0,
+                        "layer_ms": conv_ms},
+           "config": {"workload": "128^3 lognormal sigma_ln 1.5 + 16 spheres, 1 bin; 16 training "
+                                  "fields (seeds 5000+i), 4 held-out (6000+i)"}}
+    mesh.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +292,10 @@ def main():
                     help="write the march traffic summary from rocprofv3 --pmc outputs "
                          "(*_results.db or counter_collection.csv)")
     ap.add_argument("--sweeps", type=int, default=1, help="sweeps in the --traffic-from runs")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure the batched form (48 meshes) instead of the 256^3 sweep")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="measure the learned surrogate (128^3) instead of the 256^3 sweep")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(*args.traffic_from, sweeps=args.sweeps)
@@ -157,11 +308,16 @@ def main():
               "see DESIGN.md for how directions would be sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1410_0763_amd import art, media
 
     torch.cuda.set_device(0)
+    if args.batched:
+        bench_batched()
+        return
+    if args.surrogate:
+        bench_surrogate()
+        return
     m = media.plain_256()
     nb, nz, ny, nx = m.kappa.shape
     mesh = art.Mesh(nx, ny, nz, m.cell_size)

@@ -118,6 +118,17 @@ int art_sweep_stats(art_mesh *mesh, long long *segments, float *march_ms, float 
 int art_set_tuning(art_mesh *mesh, const art_tuning *t);
 int art_get_tuning(const art_mesh *mesh, art_tuning *t);
 
+/* Autotuner: for this mesh (fields set) and Nside, run a warm-up and a timed
+ * sweep (HIP events around direction setup, march and normalisation) with
+ * each candidate launch shape (candidates NULL: depth in {4, 6, 8, 12, 16} x
+ * interleave in {2, 4}, one subset, one wave), keep the fastest on the mesh,
+ * and return it in *best and its sweep time in *best_ms (either may be NULL).
+ * Candidates the mesh cannot run (local-memory limit) are skipped; on error
+ * the mesh keeps its previous tuning.  Synchronises hip_stream and holds a
+ * scratch output of nbins x cells floats while it runs. */
+int art_autotune(art_mesh *mesh, int nside, const art_tuning *candidates, int ncand,
+                 art_tuning *best, float *best_ms, void *hip_stream);
+
 /* Batched form: one launch sequence for n distinct meshes (each already
  * holding fields, each with its own shape, Nside, bins and tuning), captured
  * once into a HIP graph.  Launch w of the sequence marches wavefront w of

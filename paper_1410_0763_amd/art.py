@@ -22,7 +22,7 @@ MAX_NSIDE = 64
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
-           "art_ndirs", "art_last_error")
+           "art_ndirs", "art_last_error", "art_autotune")
 # include/art_nn.h: layers of the learned surrogate
 NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
     L.art_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_float)]
     L.art_batch_destroy.argtypes = [vp]
     L.art_ndirs.argtypes = [i]
+    L.art_autotune.argtypes = [vp, i, ctypes.POINTER(Tuning), i, ctypes.POINTER(Tuning),
+                               ctypes.POINTER(ctypes.c_float), vp]
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
@@ -170,6 +172,39 @@ class Mesh:
         _check(load().art_get_tuning(self._h, ctypes.byref(t)))
         return t.as_dict()
 
+    def autotune(self, nside: int, candidates=None, cache_path=None, stream=None) -> dict:
+        """Fastest launch shape for this mesh and Nside (art_autotune), set on
+        the mesh.  With cache_path, results persist in a JSON file keyed by
+        mesh shape, Nside and bins, and a cached entry is reused without
+        timing."""
+        import json
+        key = f"{self.shape[2]}x{self.shape[1]}x{self.shape[0]}|nside{nside}|bins{self.nbins}"
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+            if key in cache:
+                t = cache[key]["tuning"]
+                self.set_tuning(t["depth"], t["subsets"], t["waves"], t["interleave"])
+                return dict(cache[key], cached=True)
+        cands, n = None, 0
+        if candidates:
+            n = len(candidates)
+            cands = (Tuning * n)(*[Tuning(c["depth"], c["subsets"], c["waves"], c["interleave"])
+                                   for c in candidates])
+        best = Tuning()
+        ms = ctypes.c_float()
+        _check(load().art_autotune(self._h, nside, cands, n, ctypes.byref(best), ctypes.byref(ms),
+                                   _stream_ptr(stream)))
+        rec = dict(tuning=best.as_dict(), sweep_ms=ms.value)
+        if cache_path:
+            cache[key] = rec
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return dict(rec, cached=False)
+
     # -- sweeps ----------------------------------------------------------
     def alloc_outputs(self, nside: int, exit_sum: bool = False, device="cuda"):
         import torch
@@ -223,7 +258,7 @@ class Batch:
     per-mesh weight sequences or None.  Output tensors are allocated here and
     kept alive as long as the batch (the graph writes into them)."""
 
-    def __init__(self, meshes, nsides, gamma_ws=None, I_bc: float = 0.0, waves: int = 8,
+    def __init__(self, meshes, nsides, gamma_ws=None, I_bc: float = 0.0, waves: int = 1,
                  stream=None):
         L = load()
         n = len(meshes)

@@ -487,6 +487,66 @@ int art_sweep_range(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, 
     }
 }
 
+int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_tuning *best,
+                 float *best_ms, void *hip_stream)
+{
+    float *scratch = nullptr;
+    size_t cap = 0;
+    art_tuning saved{};
+    if (m) saved = m->tune;
+    auto done = [&](int rc) {
+        if (scratch) (void)hipFree(scratch);
+        if (rc != ART_OK && m) {
+            m->tune = saved;
+            m->desc_valid = false;
+        }
+        return rc;
+    };
+    try {
+        int rc = check_mesh_ready(m, nside);
+        if (rc) return rc;
+        std::vector<art_tuning> list;
+        if (cand) {
+            if (ncand < 1) return fail(ART_E_INVAL, "autotune: ncand must be positive");
+            list.assign(cand, cand + ncand);
+        } else {
+            for (int depth : {4, 6, 8, 12, 16})
+                for (int k : {2, 4}) list.push_back(art_tuning{depth, 1, 1, k});
+        }
+        if ((rc = dev_alloc(&scratch, (size_t)m->ncell * m->nb, &cap))) return done(rc);
+        const int nd = 12 * nside * nside;
+        float best_t = INFINITY;
+        art_tuning bt = saved;
+        for (const art_tuning &t : list) {
+            if (validate_tuning(t, m->nb) != ART_OK) continue;     // the mesh cannot run it
+            m->tune = t;
+            m->desc_valid = false;
+            for (int rep = 0; rep < 2; ++rep)                        // warm-up, then timed
+                if ((rc = art_sweep_range(m, nside, 0, nd, 0.0f, scratch, nullptr, hip_stream)))
+                    return done(rc);
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(m->ev[3]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, m->ev[0], m->ev[3]);
+            if (e != hipSuccess) return done(fail(ART_E_HIP, std::string("autotune: ") + hipGetErrorString(e)));
+            if (ms < best_t) {
+                best_t = ms;
+                bt = t;
+            }
+        }
+        if (!(best_t < INFINITY)) return done(fail(ART_E_INVAL, "autotune: no candidate can run on this mesh"));
+        m->tune = bt;
+        m->desc_valid = false;
+        if (best) *best = bt;
+        if (best_ms) *best_ms = best_t;
+        g_err.clear();
+        return done(ART_OK);
+    } catch (const std::bad_alloc &) {
+        return done(fail(ART_E_NOMEM, "host allocation failed"));
+    } catch (...) {
+        return done(fail(ART_E_HIP, "unexpected exception"));
+    }
+}
+
 int art_set_tuning(art_mesh *m, const art_tuning *t)
 {
     if (!m || !t) return fail(ART_E_INVAL, "null argument");
