@@ -3,10 +3,11 @@
 // ReLU gradient, mean-squared-error loss, AdamW, and the feature transforms.
 //
 // Forward (and input gradient, which is the same operation with mirrored
-// taps and swapped channels): an implicit GEMM.  One wave computes 32
-// consecutive voxels along x times the 32 output channels as one
-// 32 x 32 x 16 MFMA accumulator; the K loop runs over the 27 taps and the
-// input channels in groups of 16.  Each lane feeds 8 input channels of one
+// taps and swapped channels): an implicit GEMM.  One wave computes four rows
+// of 32 consecutive voxels along x times the 32 output channels as four
+// 32 x 32 x 16 MFMA accumulators; the K loop runs over the 27 taps and the
+// input channels in groups of 16, each input row and weight fragment loaded
+// once per (dz, dx) and used by up to four MFMAs.  Each lane feeds 8 input channels of one
 // voxel (one 16-byte load of the channels-last activations) and 8 input
 // channels of one output channel's weights; neighbours outside the mesh are
 // read through a buffer descriptor at an offset beyond its range, which
@@ -59,6 +60,10 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsi
 // (the lane holds column lane % 32).
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
+// One wave: 4 output rows (y0 .. y0+3 at one z) x 32 voxels along x x 32
+// output channels.  For each (dz, dx) and group of 16 input channels the 6
+// input rows y0-1 .. y0+4 and the 3 weight fragments (dy = -1, 0, 1) are
+// loaded once and feed 12 MFMAs.
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
                                                        const uint16_t *__restrict__ w,
@@ -67,56 +72,81 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
                                                        uint16_t *__restrict__ y,
                                                        float *__restrict__ y0)
 {
+    constexpr int R = 4;
     __shared__ float tile[4][32][33];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ntw = W / 32;
-    const long long ntiles = (long long)D * H * ntw;
+    const int ntw = W / 32, nty = (H + R - 1) / R;
+    const long long ntiles = (long long)D * nty * ntw;
     const long long tid = (long long)blockIdx.x * 4 + wave;
     const bool active = tid < ntiles;
     const long long t = active ? tid : 0;
-    const int xt = (int)(t % ntw), yy0 = (int)((t / ntw) % H), zz0 = (int)(t / ((long long)ntw * H));
+    const int xt = (int)(t % ntw), ty = (int)((t / ntw) % nty), zz0 = (int)(t / ((long long)ntw * nty));
+    const int yb = ty * R;
     const int m = lane & 31, kh = lane >> 5;
     const long long V = (long long)D * H * W;
     const rsrc_t rX = nn_rsrc(x, V * CIN * 2);
     const rsrc_t rW = nn_rsrc(w, 27ll * 32 * CIN * 2);
-    f32x16 acc = {};
-    for (int tap = 0; tap < 27; ++tap) {
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const int zz = zz0 + dz, yy = yy0 + dy, xx = xt * 32 + m + dx;
-        const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const unsigned aoff = ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2) : NN_OOB;
+    f32x16 acc[R];
 #pragma unroll
-        for (int ks = 0; ks < CIN / 16; ++ks) {
-            const bf16x8 a = load8(rX, aoff + (16 * ks + 8 * kh) * 2);
-            const bf16x8 b = load8(rW, (unsigned)(((tap * 32 + m) * CIN + 16 * ks + 8 * kh) * 2));
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    for (int q = 0; q < R; ++q) acc[q] = f32x16{};
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int zz = zz0 + dz;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int xx = xt * 32 + m + dx;
+            const bool okzx = zz >= 0 && zz < D && xx >= 0 && xx < W;
+#pragma unroll
+            for (int ks = 0; ks < CIN / 16; ++ks) {
+                bf16x8 a[R + 2];
+#pragma unroll
+                for (int r = 0; r < R + 2; ++r) {
+                    const int yy = yb - 1 + r;
+                    const bool ok = okzx && yy >= 0 && yy < H;
+                    const unsigned off =
+                        ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2) : NN_OOB;
+                    a[r] = load8(rX, off + (16 * ks + 8 * kh) * 2);
+                }
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    const bf16x8 bw = load8(rW, (unsigned)(((tap * 32 + m) * CIN + 16 * ks + 8 * kh) * 2));
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q + dy + 1], bw, acc[q], 0, 0, 0);
+                }
+            }
         }
     }
     const float bm = bias ? bias[m] : 0.0f;
+    for (int q = 0; q < R; ++q) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        float v = acc[r] + bm;
-        if (relu) v = fmaxf(v, 0.0f);
-        tile[wave][acc_row(r, lane)][m] = v;
-    }
-    __syncthreads();
-    if (!active) return;
-    const long long v0 = ((long long)zz0 * H + yy0) * W + xt * 32;
-    if (y) {
-        const int row = lane >> 1, c0 = (lane & 1) * 16;
-        u32x4 p[2];
+        for (int r = 0; r < 16; ++r) {
+            float v = acc[q][r] + bm;
+            if (relu) v = fmaxf(v, 0.0f);
+            tile[wave][acc_row(r, lane)][m] = v;
+        }
+        __syncthreads();
+        const int yq = yb + q;
+        if (active && yq < H) {
+            const long long v0 = ((long long)zz0 * H + yq) * W + xt * 32;
+            if (y) {
+                const int row = lane >> 1, c0 = (lane & 1) * 16;
+                u32x4 p[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = c0 + 8 * q + 2 * e;
-                p[q][e] = (unsigned)f2bf(tile[wave][row][c]) | ((unsigned)f2bf(tile[wave][row][c + 1]) << 16);
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = c0 + 8 * h + 2 * e;
+                        p[h][e] = (unsigned)f2bf(tile[wave][row][c]) |
+                                  ((unsigned)f2bf(tile[wave][row][c + 1]) << 16);
+                    }
+                u32x4 *dst = reinterpret_cast<u32x4 *>(y + (v0 + row) * 32 + c0);
+                dst[0] = p[0];
+                dst[1] = p[1];
             }
-        u32x4 *dst = reinterpret_cast<u32x4 *>(y + (v0 + row) * 32 + c0);
-        dst[0] = p[0];
-        dst[1] = p[1];
+            if (y0 && lane < 32) y0[v0 + lane] = tile[wave][lane][0];
+        }
+        __syncthreads();
     }
-    if (y0 && lane < 32) y0[v0 + lane] = tile[wave][lane][0];
 }
 
 template <int CIN>
@@ -405,7 +435,7 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
     if ((long long)D * H * W * 64 >= (1ll << 31))
         return art_set_error(ART_E_UNSUPPORTED, "art_conv3d_fwd: activation tensor above 2 GiB");
     hipStream_t st = (hipStream_t)hip_stream;
-    const long long tiles = (long long)D * H * (W / 32);
+    const long long tiles = (long long)D * ((H + 3) / 4) * (W / 32);
     const auto *xp = (const uint16_t *)x;
     const auto *wp = (const uint16_t *)w_k;
     if (cin == 16)
