@@ -49,7 +49,8 @@ int art_nn_bias_grad(const void *g, int V, float *partial, int nchunk, float *db
                      void *hip_stream);
 
 /* xs[s][c][v] = x[v + (s - 1) along x][c] (zero outside the mesh), s = 0..2:
- * the channels-first copies the weight gradient reads.  x: bf16 [V][cin]. */
+ * the channels-first copies the weight gradient reads.  x: bf16 [V][cin],
+ * cin = 16 or 32. */
 int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *hip_stream);
 
 /* Gradient at a layer output: g = dy where y > 0 (the ReLU of the forward

@@ -149,6 +149,8 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
     }
 }
 
+// One wave: the three taps dx = -1, 0, 1 of one (dz, dy) over one chunk of
+// rows; the gradient operand is loaded once per K step for three MFMAs.
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_bwdw_kernel(const uint16_t *__restrict__ xs,
                                                         const uint16_t *__restrict__ g, int D,
@@ -157,33 +159,42 @@ __global__ __launch_bounds__(256) void conv_bwdw_kernel(const uint16_t *__restri
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long job = (long long)blockIdx.x * 4 + wave;
-    if (job >= 27ll * nchunk) return;                      // whole wave
-    const int tap = (int)(job % 27), chunk = (int)(job / 27);
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    if (job >= 9ll * nchunk) return;                       // whole wave
+    const int zy = (int)(job % 9), chunk = (int)(job / 9);
+    const int dz = zy / 3 - 1, dy = zy % 3 - 1;
     const int m = lane & 31, kh = lane >> 5;
     const long long V = (long long)D * H * W;
     const rsrc_t rX = nn_rsrc(xs, 3ll * CIN * V * 2);
     const rsrc_t rG = nn_rsrc(g, 32ll * V * 2);
-    const long long abase = ((long long)(dx + 1) * CIN + m) * V;   // elements
     const long long gbase = (long long)m * V;
     const int rows = D * H / nchunk;
-    f32x16 acc = {};
+    f32x16 acc[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) acc[s] = f32x16{};
     for (int r = chunk * rows; r < (chunk + 1) * rows; ++r) {
         const int z = r / H, yv = r % H;
         const int zz = z + dz, yy = yv + dy;
         const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && m < CIN;
-        const long long arow = abase + ((long long)zz * H + yy) * W + 8 * kh;
+        const long long arow = ((long long)zz * H + yy) * W + 8 * kh;   // within one copy
         const long long grow = gbase + (long long)r * W + 8 * kh;
         for (int x0 = 0; x0 < W; x0 += 16) {
-            const bf16x8 a = load8(rX, ok ? (unsigned)((arow + x0) * 2) : NN_OOB);
             const bf16x8 b = load8(rG, (unsigned)((grow + x0) * 2));
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const long long aoff = ((long long)s * CIN + m) * V + arow + x0;
+                const bf16x8 a = load8(rX, ok ? (unsigned)(aoff * 2) : NN_OOB);
+                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[s], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int ci = acc_row(q, lane);
-        if (ci < CIN) partial[(((long long)chunk * 27 + tap) * CIN + ci) * 32 + m] = acc[q];
+    for (int s = 0; s < 3; ++s) {
+        const int tap = zy * 3 + s;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int ci = acc_row(q, lane);
+            if (ci < CIN) partial[(((long long)chunk * 27 + tap) * CIN + ci) * 32 + m] = acc[s][q];
+        }
     }
 }
 
@@ -219,30 +230,53 @@ __global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *__res
     }
 }
 
+// One thread per (voxel, group of 8 channels): a 16-byte load of the
+// channels-last input, eight 2-byte stores into each channels-first copy.
 __global__ void shift3_kernel(const uint16_t *__restrict__ x, int cin, int W, long long V,
                               uint16_t *__restrict__ xs)
 {
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
+    const int ng = cin / 8;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * ng) return;
+    const long long v = t / ng;
+    const int cg = (int)(t % ng);
     const int xx = (int)(v % W);
     for (int s = 0; s < 3; ++s) {
         const int sx = xx + s - 1;
-        const bool ok = sx >= 0 && sx < W;
-        for (int c = 0; c < cin; ++c)
-            xs[((long long)s * cin + c) * V + v] = ok ? x[(v + s - 1) * cin + c] : (uint16_t)0;
+        u32x4 d = {0u, 0u, 0u, 0u};
+        if (sx >= 0 && sx < W) d = *reinterpret_cast<const u32x4 *>(x + (v + s - 1) * cin + 8 * cg);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const unsigned word = d[e >> 1];
+            xs[((long long)s * cin + 8 * cg + e) * V + v] = (uint16_t)((e & 1) ? (word >> 16) : (word & 0xffffu));
+        }
     }
 }
 
+// One thread per (voxel, group of 8 channels): 16-byte loads and store of the
+// channels-last arrays, eight 2-byte stores into the channels-first copy.
 __global__ void relu_grad_kernel(const uint16_t *__restrict__ dy, const uint16_t *__restrict__ y,
                                  long long V, uint16_t *__restrict__ g, uint16_t *__restrict__ gcf)
 {
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    for (int c = 0; c < 32; ++c) {
-        uint16_t d = dy[v * 32 + c];
-        if (y && !(bf2f(y[v * 32 + c]) > 0.0f)) d = 0;
-        g[v * 32 + c] = d;
-        gcf[(long long)c * V + v] = d;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * 4) return;
+    const long long v = t >> 2;
+    const int cg = (int)(t & 3);
+    u32x4 d = *reinterpret_cast<const u32x4 *>(dy + v * 32 + 8 * cg);
+    if (y) {
+        const u32x4 a = *reinterpret_cast<const u32x4 *>(y + v * 32 + 8 * cg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned lo = bf2f((uint16_t)(a[k] & 0xffffu)) > 0.0f ? 0x0000ffffu : 0u;
+            const unsigned hi = bf2f((uint16_t)(a[k] >> 16)) > 0.0f ? 0xffff0000u : 0u;
+            d[k] &= lo | hi;
+        }
+    }
+    *reinterpret_cast<u32x4 *>(g + v * 32 + 8 * cg) = d;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const unsigned word = d[e >> 1];
+        gcf[(long long)(8 * cg + e) * V + v] = (uint16_t)((e & 1) ? (word >> 16) : (word & 0xffffu));
     }
 }
 
@@ -461,7 +495,7 @@ int art_conv3d_bwd_weight(const void *xs, int cin, const void *g, int D, int H, 
     hipStream_t st = (hipStream_t)hip_stream;
     const auto *xp = (const uint16_t *)xs;
     const auto *gp = (const uint16_t *)g;
-    const unsigned nb = blocks_for(27ll * nchunk, 4);
+    const unsigned nb = blocks_for(9ll * nchunk, 4);
     if (cin == 16)
         hipLaunchKernelGGL(conv_bwdw_kernel<16>, dim3(nb), dim3(256), 0, st, xp, gp, D, H, W, nchunk, partial);
     else
@@ -488,10 +522,10 @@ int art_nn_bias_grad(const void *g, int V, float *partial, int nchunk, float *db
 
 int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *hip_stream)
 {
-    if (!x || !xs || cin < 1 || cin > 32 || D < 1 || H < 1 || W < 1)
-        return art_set_error(ART_E_INVAL, "art_nn_shift3: bad arguments");
+    if (!x || !xs || (cin != 16 && cin != 32) || D < 1 || H < 1 || W < 1)
+        return art_set_error(ART_E_INVAL, "art_nn_shift3: bad arguments (cin must be 16 or 32)");
     const long long V = (long long)D * H * W;
-    hipLaunchKernelGGL(shift3_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, (hipStream_t)hip_stream,
+    hipLaunchKernelGGL(shift3_kernel, dim3(blocks_for(V * (cin / 8), 256)), dim3(256), 0, (hipStream_t)hip_stream,
                        (const uint16_t *)x, cin, W, V, (uint16_t *)xs);
     return launch_status("art_nn_shift3");
 }
@@ -499,7 +533,7 @@ int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *h
 int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *g_cf, void *hip_stream)
 {
     if (!dy || !g || !g_cf || V < 1) return art_set_error(ART_E_INVAL, "art_nn_relu_grad: bad arguments");
-    hipLaunchKernelGGL(relu_grad_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, (hipStream_t)hip_stream,
+    hipLaunchKernelGGL(relu_grad_kernel, dim3(blocks_for(4ll * V, 256)), dim3(256), 0, (hipStream_t)hip_stream,
                        (const uint16_t *)dy, (const uint16_t *)y, (long long)V, (uint16_t *)g,
                        (uint16_t *)g_cf);
     return launch_status("art_nn_relu_grad");

@@ -46,6 +46,7 @@ class Surrogate:
         self.V = D * H * W
         rows = D * H
         self.nchunk = nchunk or max(c for c in (512, 256, 128, 64, 32, 16, 8, 4, 2, 1) if rows % c == 0)
+        self.nchunk_b = max(c for c in (1024, 512, 256, 128, 64, 32, 16, 8, 4, 2, 1) if self.V % c == 0)
         dev = "cuda"
         rng = np.random.default_rng(seed)
         self.w, self.b = [], []
@@ -72,7 +73,7 @@ class Surrogate:
         self.gcf = torch.zeros((32, V), dtype=i16, device=dev)
         self.xs = torch.zeros((3, 32, V), dtype=i16, device=dev)
         self.partial = torch.zeros(self.nchunk * 27 * 32 * 32, dtype=torch.float32, device=dev)
-        self.bpart = torch.zeros(self.nchunk * 32, dtype=torch.float32, device=dev)
+        self.bpart = torch.zeros(self.nchunk_b * 32, dtype=torch.float32, device=dev)
         self.dw = [torch.zeros_like(t) for t in self.w]
         self.db = [torch.zeros_like(t) for t in self.b]
         self.mpart = torch.zeros(256, dtype=torch.float32, device=dev)
@@ -112,7 +113,7 @@ class Surrogate:
             nn.shift3(xin, CIN[l], self.shape, self.xs)
             nn.conv3d_bwd_weight(self.xs, CIN[l], self.gcf, self.shape, self.partial, self.nchunk,
                                  self.dw[l])
-            nn.bias_grad(self.gcf, self.V, self.bpart, self.nchunk, self.db[l])
+            nn.bias_grad(self.gcf, self.V, self.bpart, self.nchunk_b, self.db[l])
             if l > 0:
                 nn.conv3d_fwd(self.g, 32, self.w_bwd[l], None, self.shape, 0, y=self.dy[1 - cur])
                 cur = 1 - cur
