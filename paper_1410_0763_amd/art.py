@@ -28,6 +28,12 @@ NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "ar
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
               "art_nn_features", "art_nn_expand", "art_nn_log_ratio", "art_nn_ood_count",
               "art_nn_sq_weights")
+# include/art_surrogate.h: the surrogate object, its gate and checkpoints
+SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_params",
+              "art_surrogate_set_stats", "art_surrogate_get_stats", "art_surrogate_fit_stats",
+              "art_surrogate_features", "art_surrogate_make_pair", "art_surrogate_gradients",
+              "art_surrogate_train_step", "art_surrogate_infer", "art_surrogate_param",
+              "art_surrogate_save", "art_surrogate_load", "art_sweep_surrogate", "art_sha256")
 
 
 class ArtError(RuntimeError):
@@ -93,7 +99,25 @@ def load(path: str = LIB_PATH):
     L.art_nn_expand.argtypes = [vp, vp, i, vp, vp]
     L.art_nn_log_ratio.argtypes = [vp, vp, i, vp, vp]
     L.art_nn_ood_count.argtypes = [vp, i, fp, fp, vp, vp]
-    for name in EXPORTS + NN_EXPORTS:
+    cp, ip = ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)
+    L.art_surrogate_create.argtypes = [i, i, i, ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    L.art_surrogate_destroy.argtypes = [vp]
+    L.art_surrogate_n_params.argtypes = [vp]
+    L.art_surrogate_set_stats.argtypes = [vp, fp, fp, fp, fp, f]
+    L.art_surrogate_get_stats.argtypes = [vp, fp, fp, fp, fp, fp]
+    L.art_surrogate_fit_stats.argtypes = [vp, i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                          ctypes.POINTER(vp), f, vp]
+    L.art_surrogate_features.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.art_surrogate_make_pair.argtypes = [vp, vp, i, i, f, vp, vp, vp, vp, vp]
+    L.art_surrogate_gradients.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.art_surrogate_train_step.argtypes = [vp, vp, vp, vp, f, f, vp, vp]
+    L.art_surrogate_infer.argtypes = [vp, vp, vp, vp]
+    L.art_surrogate_param.argtypes = [vp, i, i, vp, i, vp]
+    L.art_surrogate_save.argtypes = [vp, cp, vp]
+    L.art_surrogate_load.argtypes = [vp, cp, vp]
+    L.art_sweep_surrogate.argtypes = [vp, vp, i, i, vp, f, ctypes.POINTER(Outputs), ip, fp, vp]
+    L.art_sha256.argtypes = [vp, ctypes.c_ulonglong, vp]
+    for name in EXPORTS + NN_EXPORTS + SG_EXPORTS:
         if name != "art_last_error":
             getattr(L, name).restype = i
     _lib = L

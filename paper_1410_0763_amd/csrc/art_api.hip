@@ -94,6 +94,16 @@ struct art_mesh {
     bool desc_valid = false;
 };
 
+void art_mesh_fields(const art_mesh *m, int dims[3], int *nb, double *h, const float4 **fields)
+{
+    dims[0] = m->nx;
+    dims[1] = m->ny;
+    dims[2] = m->nz;
+    *nb = m->nb;
+    *h = m->h;
+    *fields = m->nb > 0 ? m->fields : nullptr;
+}
+
 namespace {
 
 int nblocks(int n, int b) { return (n + b - 1) / b; }

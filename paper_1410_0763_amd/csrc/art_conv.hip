@@ -395,15 +395,7 @@ __global__ void features_kernel(const float *__restrict__ J, const float *__rest
 {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const float f[3] = {J[v], kap[v], S[v]};
-    unsigned w[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    uint16_t h[3];
-    for (int k = 0; k < 3; ++k) h[k] = f2bf((logf(fmaxf(f[k], 1e-30f)) - mu.a[k]) * isd.a[k]);
-    w[0] = (unsigned)h[0] | ((unsigned)h[1] << 16);
-    w[1] = (unsigned)h[2];
-    u32x4 *dst = reinterpret_cast<u32x4 *>(x + v * 16);
-    dst[0] = u32x4{w[0], w[1], w[2], w[3]};
-    dst[1] = u32x4{w[4], w[5], w[6], w[7]};
+    art_feature_store(J[v], kap[v], S[v], mu.a, isd.a, x + v * 16);
 }
 
 __global__ void expand_kernel(const float *__restrict__ Jc, const float *__restrict__ pred,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+typedef struct art_mesh art_mesh;
+
 // One direction of the HEALPix set with its parallel-ray lattice (Sect. 2.2,
 // 2.3).  Ray (j,k) is the line x_i(s) = alpha_i + beta_i s over depth s in
 // [0, N_a]: along the dominant axis a, alpha_a is the upstream face (0 or N_a)
@@ -74,3 +76,29 @@ int art_max_bucket_dirs(int nside, int subsets);
 int art_set_error(int code, const char *msg);
 int art_march_max_lds_bytes();
 int art_march_lds_floats(int depth, int nb);
+// Shape, bins, cell size and device field records ([cell][nb] {kappa h,
+// 1/(kappa h), S, 0}; NULL before art_set_fields) of a mesh.
+void art_mesh_fields(const art_mesh *mesh, int dims[3], int *nb, double *h, const float4 **fields);
+
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t art_bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Input record of the surrogate network for one cell, 16 bf16 channels:
+// channel k < 3 is (log(max(f_k, 1e-30)) - mu[k]) * isd[k] for
+// f = (J, kappa, S), the other 13 are 0.
+__device__ __forceinline__ void art_feature_store(float J, float kappa, float S, const float *mu,
+                                                  const float *isd, uint16_t *x16)
+{
+    const float f[3] = {J, kappa, S};
+    uint16_t h[3];
+    for (int k = 0; k < 3; ++k) h[k] = art_bf16_rne((logf(fmaxf(f[k], 1e-30f)) - mu[k]) * isd[k]);
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 *dst = reinterpret_cast<u4 *>(x16);
+    dst[0] = u4{(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2], 0u, 0u};
+    dst[1] = u4{0u, 0u, 0u, 0u};
+}

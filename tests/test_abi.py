@@ -26,11 +26,45 @@ def test_nn_header_and_binding_agree():
     assert _declared("art_nn.h") == sorted(art.NN_EXPORTS)
 
 
+def test_surrogate_header_and_binding_agree():
+    from paper_1410_0763_amd import art
+    assert _declared("art_surrogate.h") == sorted(art.SG_EXPORTS)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1410_0763_amd import art
     L = art.load()
-    for name in _declared() + _declared("art_nn.h"):
+    for name in _declared() + _declared("art_nn.h") + _declared("art_surrogate.h"):
         assert hasattr(L, name), name
+
+
+def test_checkpoint_digest_is_sha256():
+    """The checkpoint digest against hashlib's SHA-256, across the padding
+    boundaries (55, 56, 63, 64 bytes) and several blocks."""
+    import hashlib
+    import random
+    from paper_1410_0763_amd import surrogate as SG
+    rnd = random.Random(3)
+    for n in (0, 1, 3, 55, 56, 57, 63, 64, 65, 119, 120, 128, 1000, 65537):
+        data = bytes(rnd.getrandbits(8) for _ in range(n))
+        assert SG.sha256(data) == hashlib.sha256(data).digest(), n
+
+
+def test_surrogate_argument_checks_without_gpu():
+    """Shapes and arguments the surrogate cannot take are rejected before any
+    device call."""
+    from paper_1410_0763_amd import art
+    L = art.load()
+    h = ctypes.c_void_p()
+    assert L.art_surrogate_create(48, 8, 8, 0, ctypes.byref(h)) == -1          # nx not a multiple of 32
+    assert b"multiple of 32" in L.art_last_error()
+    assert L.art_surrogate_create(32, 0, 8, 0, ctypes.byref(h)) == -1
+    assert L.art_surrogate_create(32, 8, 8, 0, None) == -1
+    assert L.art_surrogate_create(320, 320, 320, 0, ctypes.byref(h)) == -5     # above the 2 GiB buffers
+    assert L.art_surrogate_n_params(None) == -1
+    assert L.art_surrogate_destroy(None) == 0
+    assert L.art_sweep_surrogate(None, None, 2, 16, None, 1.0, None, None, None, None) == -1
+    assert L.art_sha256(None, 5, ctypes.create_string_buffer(32)) == -1
 
 
 def test_nn_argument_checks_without_gpu():

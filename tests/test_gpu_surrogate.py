@@ -192,24 +192,27 @@ def test_network_gradients_match_reference():
     shape = (4, 4, 32)
     V = 4 * 4 * 32
     model = SG.Surrogate(shape, seed=1)
-    model.w[5][:, :, 0].normal_(0.0, 0.05)     # so that every layer gets a gradient
     rng = np.random.default_rng(5)
+    w5 = model.param(5, SG.W).cpu().numpy()
+    w5[:, :, 0] = rng.normal(0.0, 0.05, size=w5[:, :, 0].shape)   # so that every layer gets a gradient
+    model.set_param(5, SG.W, _dev(w5))
     xf = np.zeros((V, 16), np.float32)
     xf[:, :3] = rng.normal(size=(V, 3))
     xb = bf16_bits(xf)
     tgt = rng.normal(size=V).astype(np.float32)
     loss = model.gradients(_dev(xb), _dev(tgt))
     torch.cuda.synchronize()
-    layers = [(bf16_value(bf16_bits(model.w[l].cpu().numpy())),
-               model.b[l].cpu().numpy().astype(np.float64)) for l in range(6)]
+    layers = [(bf16_value(bf16_bits(model.param(l, SG.W).cpu().numpy())),
+               model.param(l, SG.B).cpu().numpy().astype(np.float64)) for l in range(6)]
     x_ref = bf16_value(xb).reshape(4, 4, 32, 16)
     rl, rg = _faithful_grads(x_ref, layers, tgt.reshape(4, 4, 32).astype(np.float64), V)
     print(f"loss gpu {loss.item():.6e} ref {rl:.6e}", flush=True)
     errs = []
     for l in range(6):
-        dw = model.dw[l].cpu().numpy()
+        dw = model.param(l, SG.DW).cpu().numpy()
+        db = model.param(l, SG.DB).cpu().numpy()
         e = np.linalg.norm(dw - rg[l][0]) / np.linalg.norm(rg[l][0])
-        eb = np.linalg.norm(model.db[l].cpu().numpy() - rg[l][1]) / max(np.linalg.norm(rg[l][1]), 1e-30)
+        eb = np.linalg.norm(db - rg[l][1]) / max(np.linalg.norm(rg[l][1]), 1e-30)
         print(f"layer {l}: relative weight-gradient error {e:.2e}, bias {eb:.2e}", flush=True)
         errs.append(max(e, eb))
     # a bf16 rounding that falls the other way under float32 sums (a few
@@ -238,12 +241,16 @@ def test_training_reduces_loss():
 
 
 def test_checkpoint_roundtrip(tmp_path):
+    """Save / load restores weights, moments, step and statistics exactly;
+    corrupted, truncated, foreign and wrong-shape files are rejected and leave
+    the surrogate unchanged."""
     _case("checkpoint save / load")
     import torch
+    from paper_1410_0763_amd import art
     from paper_1410_0763_amd import surrogate as SG
     shape = (4, 4, 32)
     a = SG.Surrogate(shape, seed=3)
-    a.set_stats([0, 0, 0], [1, 1, 1], [-5, -5, -5], [5, 5, 5], 0.1)
+    a.set_stats([0.5, -1, 2], [1, 2, 3], [-5, -5, -5], [5, 5, 5], 0.1)
     rng = np.random.default_rng(1)
     V = 4 * 4 * 32
     xf = np.zeros((V, 16), np.float32)
@@ -256,17 +263,104 @@ def test_checkpoint_roundtrip(tmp_path):
     a.save(str(p))
     b = SG.Surrogate(shape, seed=99)
     b.load(str(p))
+    assert b.stats == a.stats
     for _ in range(2):
         la = a.train_step(x, tgt).item()
         lb = b.train_step(x, tgt).item()
     torch.cuda.synchronize()
     assert la == lb
-    assert all(torch.equal(u, v) for u, v in zip(a.w, b.w))
-    raw = bytearray(p.read_bytes())
-    raw[-1] ^= 1
-    p.write_bytes(bytes(raw))
-    with pytest.raises(ValueError):
-        SG.Surrogate(shape).load(str(p))
+    for l in range(6):
+        for what in (SG.W, SG.B):
+            assert torch.equal(a.param(l, what), b.param(l, what))
+    c = SG.Surrogate(shape, seed=7)
+    before = c.param(0, SG.W).clone()
+    raw = p.read_bytes()
+    bad = bytearray(raw)
+    bad[-1] ^= 1
+    cases = {"checksum": bytes(bad), "size": raw[:-4], "not a surrogate": b"XXXXXXXX" + raw[8:]}
+    for what, data in cases.items():
+        p.write_bytes(data)
+        with pytest.raises(art.ArtError) as e:
+            c.load(str(p))
+        assert e.value.code == -1 and what in str(e.value), str(e.value)
+    assert torch.equal(c.param(0, SG.W), before)
+    p.write_bytes(raw)
+    with pytest.raises(art.ArtError, match="shape"):
+        SG.Surrogate((8, 4, 32)).load(str(p))
+
+
+def test_gate_and_argument_errors():
+    """Without a held-out error the gate always falls back; exit sums and
+    meshes of another shape or bin count are rejected."""
+    _case("gate defaults and argument errors")
+    import torch
+    from paper_1410_0763_amd import art
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (8, 8, 32)
+    rng = np.random.default_rng(4)
+    k = torch.from_numpy(rng.uniform(0.05, 2.0, (1,) + shape).astype(np.float32)).cuda()
+    s = torch.from_numpy(rng.uniform(0.0, 1.0, (1,) + shape).astype(np.float32)).cuda()
+    mesh = art.Mesh(32, 8, 8)
+    mesh.set_fields(k, s)
+    model = SG.Surrogate(shape, seed=0)
+    out, fb, est = SG.sweep_surrogate(mesh, model, 1, 2, err_bound=1e9)
+    assert fb and np.isnan(est)
+    ref = mesh.sweep(2)
+    torch.cuda.synchronize()
+    for key in ("J", "J_in", "J_exact", "Gamma"):
+        assert torch.equal(out[key], ref[key]), key
+    model.set_val_err(0.0)
+    out, fb, est = SG.sweep_surrogate(mesh, model, 1, 2, err_bound=1e9)
+    assert not fb and est == 0.0
+    o = mesh.alloc_outputs(2, exit_sum=True)
+    outs = art.Outputs(*(art._ptr(o.get(q)) for q in ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
+    rc = art.load().art_sweep_surrogate(mesh._h, model._h, 1, 2, None, 1e9, outs, None, None,
+                                        art._stream_ptr(None))
+    assert rc == -1 and b"exit" in art.load().art_last_error()
+    other = art.Mesh(32, 8, 4)
+    other.set_fields(k[:, :4].contiguous(), s[:, :4].contiguous())
+    with pytest.raises(art.ArtError, match="shape"):
+        SG.sweep_surrogate(other, model, 1, 2)
+    two = art.Mesh(32, 8, 8)
+    two.set_fields(torch.cat([k, k]), torch.cat([s, s]))
+    with pytest.raises(art.ArtError, match="one bin"):
+        SG.sweep_surrogate(two, model, 1, 2)
+    for m in (mesh, other, two):
+        m.close()
+
+
+def test_fit_stats_matches_numpy():
+    """Feature statistics of the library against float64 numpy on the same
+    float32 inputs (the log is taken in float32 on the GPU)."""
+    _case("feature statistics")
+    import torch
+    from paper_1410_0763_amd import surrogate as SG
+    shape = (8, 16, 32)
+    V = 8 * 16 * 32
+    rng = np.random.default_rng(12)
+    fields = [[rng.lognormal(0.0, 1.5, V).astype(np.float32) for _ in range(3)] for _ in range(3)]
+    fields[1][1][:7] = 0.0                      # vacuum cells: log floored at 1e-30
+    model = SG.Surrogate(shape, seed=0)
+    model.fit_stats(*[[_dev(f[c]) for f in fields] for c in range(3)], margin=0.5)
+    st = model.stats
+    logs = np.stack([np.concatenate([np.log(np.maximum(f[c].astype(np.float64), 1e-30)) for f in fields])
+                     for c in range(3)])
+    mu, sd = logs.mean(1), logs.std(1)
+    z = (logs - mu[:, None]) / sd[:, None]
+    np.testing.assert_allclose(st["mu"], mu, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(st["sd"], sd, rtol=1e-5)
+    np.testing.assert_allclose(st["lo"], z.min(1) - 0.5, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(st["hi"], z.max(1) + 0.5, rtol=1e-5, atol=1e-5)
+    assert st["val_err"] is None
+    # the features of one field with these statistics, against numpy + bf16 rounding
+    x = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
+    model.features(*[_dev(fields[0][c]) for c in range(3)], x)
+    torch.cuda.synchronize()
+    ref = np.stack([(np.log(np.maximum(fields[0][c], 1e-30)).astype(np.float32) - np.float32(st["mu"][c]))
+                    * np.float32(1.0 / np.float32(st["sd"][c])) for c in range(3)], 1).astype(np.float32)
+    got = bf16_value(x.cpu().numpy()[:, :3])
+    assert np.max(np.abs(got - bf16_value(bf16_bits(ref)))) <= 2.0 ** -7 * np.max(np.abs(ref))
+    assert not x.cpu().numpy()[:, 3:].any()
 
 
 def _pairs(model, mesh, idx, train):
@@ -279,11 +373,10 @@ def _pairs(model, mesh, idx, train):
         k = torch.from_numpy(m.kappa).cuda()
         s = torch.from_numpy(m.S).cuda()
         mesh.set_fields(k, s)
-        x = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
         t = torch.zeros(model.V, dtype=torch.float32, device="cuda")
         w = torch.zeros(model.V, dtype=torch.float32, device="cuda")
-        Jc, Jf = SG.make_pair(mesh, k, s, 2, 16, model, x, t, w)
-        out.append(dict(m=m, k=k, s=s, x=x, t=t, w=w, Jc=Jc.clone(), Jf=Jf.clone()))
+        Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w)
+        out.append(dict(m=m, k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf))
     return out
 
 
@@ -303,19 +396,12 @@ def test_surrogate_gain_and_fallback():
     shape = (128, 128, 128)
     model = SG.Surrogate(shape, seed=0)
     mesh = art.Mesh(*shape[::-1])
-    model.set_stats([0, 0, 0], [1, 1, 1], [-1e9] * 3, [1e9] * 3)
     train = _pairs(model, mesh, range(16), True)
-    # feature statistics from the first fields (host side, float64)
-    feats = []
-    for p in train[:2]:
-        feats.append(np.stack([np.log(np.maximum(p["Jc"].cpu().numpy(), 1e-30)),
-                               np.log(np.maximum(p["m"].kappa.ravel(), 1e-30)),
-                               np.log(np.maximum(p["m"].S.ravel(), 1e-30))]))
-    f = np.concatenate(feats, axis=1)
-    mu, sd = f.mean(axis=1), f.std(axis=1)
-    z = (f - mu[:, None]) / sd[:, None]
-    model.set_stats(mu, sd, z.min(axis=1) - 1.0, z.max(axis=1) + 1.0)
-    for p in train:                       # features again with the statistics
+    # feature statistics from the first fields, then the network inputs
+    model.fit_stats([p["Jc"] for p in train[:2]], [p["k"].reshape(-1) for p in train[:2]],
+                    [p["s"].reshape(-1) for p in train[:2]], margin=1.0)
+    for p in train:
+        p["x"] = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
         model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), p["x"])
     test = _pairs(model, mesh, range(3), False)
     steps = 800
@@ -328,11 +414,12 @@ def test_surrogate_gain_and_fallback():
     print(f"trained {steps} steps in {time.perf_counter() - t0:.1f} s, last loss {loss.item():.4e}",
           flush=True)
     err_c, err_s, lr_c, lr_s = [], [], [], []
+    model.set_val_err(0.0)
     for p in test:
         mesh.set_fields(p["k"], p["s"])
-        model.stats["val_err"] = 0.0
-        J, fb, est = SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1e9)
+        out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1e9)
         assert not fb
+        J = out["J"].reshape(-1)
         Jf = p["Jf"]
         err_s.append((torch.linalg.norm(J - Jf) / torch.linalg.norm(Jf)).item())
         err_c.append((torch.linalg.norm(p["Jc"] - Jf) / torch.linalg.norm(Jf)).item())
@@ -344,15 +431,29 @@ def test_surrogate_gain_and_fallback():
           flush=True)
     assert np.mean(lr_s) < 0.75 * np.mean(lr_c)
     assert np.mean(err_s) < 1.25 * np.mean(err_c)
-    model.stats["val_err"] = float(np.mean(err_s))
-    # time: coarse sweep + inference against the fine sweep
+    model.set_val_err(float(np.mean(err_s)))
+    # the accepted outputs against the same steps through the other entry points
     p = test[0]
     mesh.set_fields(p["k"], p["s"])
-    SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1.0)
+    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0, gamma_w=[0.5])
+    assert not fb
+    c = mesh.sweep(2)
+    x = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
+    model.features(c["J"].reshape(-1), p["k"].reshape(-1), p["s"].reshape(-1), x)
+    Jm = c["J"].reshape(-1) * torch.exp(model.forward(x))
+    torch.cuda.synchronize()
+    Js = out["J"].reshape(-1)
+    assert torch.allclose(Js, Jm, rtol=2e-6, atol=0)
+    assert torch.allclose(out["J_in"].reshape(-1), Js - p["s"].reshape(-1), rtol=0, atol=1e-6 * Js.max().item())
+    assert torch.allclose(out["Gamma"].reshape(-1), 0.5 * Js, rtol=1e-6, atol=0)
+    assert torch.allclose(out["J_exact"].reshape(-1), Js + (c["J_exact"] - c["J"]).reshape(-1),
+                          rtol=0, atol=1e-6 * Js.max().item())
+    # time: coarse sweep + inference against the fine sweep
+    SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(3):
-        SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=1.0)
+        SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0)
     torch.cuda.synchronize()
     t_sur = (time.perf_counter() - t0) / 3
     mesh.sweep(16)
@@ -365,11 +466,11 @@ def test_surrogate_gain_and_fallback():
     print(f"coarse + inference {1e3 * t_sur:.1f} ms, fine sweep {1e3 * t_fine:.1f} ms", flush=True)
     assert t_sur < t_fine
     # forced fallbacks: bound 0, and an out-of-distribution (vacuum) field
-    J, fb, est = SG.sweep_surrogate(mesh, model, p["k"], p["s"], err_bound=0.0)
-    assert fb and torch.allclose(J, p["Jf"], rtol=1e-6, atol=0)
+    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=0.0)
+    assert fb and torch.allclose(out["J"].reshape(-1), p["Jf"], rtol=1e-6, atol=0)
     vac_k = torch.zeros_like(p["k"])
     mesh.set_fields(vac_k, p["s"])
-    J, fb, est = SG.sweep_surrogate(mesh, model, vac_k, p["s"], err_bound=0.5)
+    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=0.5)
     print(f"vacuum field: used_fallback {fb}, estimated error {est:.3f}", flush=True)
     assert fb
     mesh.close()
