@@ -70,7 +70,8 @@ struct art_mesh {
     art_tuning tune{8, 1, 1, 4};
     int mbd = 0, mbd_key[2] = {-1, -1};   // largest bucket (directions) for (nside, subsets)
 
-    float4 *fields = nullptr; size_t fields_cap = 0;
+    float2 *fields = nullptr; size_t fields_cap = 0;
+    float2 *fields_t = nullptr; size_t fields_t_cap = 0;   // y-fastest copy
     int *bad = nullptr; size_t bad_cap = 0;
     float *stage = nullptr; size_t stage_cap = 0;   // host-upload staging
 
@@ -94,7 +95,7 @@ struct art_mesh {
     bool desc_valid = false;
 };
 
-void art_mesh_fields(const art_mesh *m, int dims[3], int *nb, double *h, const float4 **fields)
+void art_mesh_fields(const art_mesh *m, int dims[3], int *nb, double *h, const float2 **fields)
 {
     dims[0] = m->nx;
     dims[1] = m->ny;
@@ -200,9 +201,10 @@ long long state_bound(const art_mesh *m, int nd)
 int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
 {
     const int nd = 12 * nside * nside;
-    // the march addresses one bucket's ray states and one block's field
-    // records with 32-bit byte offsets from wave-uniform bases (a block spans
-    // at most depth - 1 + 7 + 7 steps of the largest cell stride nx ny)
+    // the march addresses one bucket's ray states, one block's field records
+    // and the crossing table with 32-bit byte offsets from wave-uniform bases
+    // (a block spans at most depth - 1 + 7 + 7 steps of the largest cell
+    // stride of either field copy: nx ny, or ny nz for the y-fastest copy)
     if (m->mbd_key[0] != nside || m->mbd_key[1] != m->tune.subsets) {
         m->mbd = art_max_bucket_dirs(nside, m->tune.subsets);
         m->mbd_key[0] = nside;
@@ -210,7 +212,9 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     }
     if ((long long)m->mbd * (dir_slot_bound(m) + 1) * m->nb * 4 >=
             (1ll << 31) ||
-        (m->tune.depth + 14ll) * m->nx * m->ny * m->nb * 16 >= (1ll << 31))
+        (m->tune.depth + 14ll) * std::max((long long)m->nx * m->ny, (long long)m->ny * m->nz) * m->nb * 8 >=
+            (1ll << 31) ||
+        (long long)nd * std::max(m->nx, std::max(m->ny, m->nz)) * 16 >= (1ll << 31))
         return fail(ART_E_UNSUPPORTED, "mesh too large for 32-bit offsets within a bucket of directions or a block");
     const int nbk = 24 * m->tune.subsets;
     int rc;
@@ -224,6 +228,7 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     if ((rc = build_schedule(m))) return rc;
     ArtMeshDesc d{};
     d.fields = m->fields;
+    d.fields_t = m->fields_t;
     d.state = m->state;
     d.acc = m->acc;
     d.dirs = m->dirs;
@@ -231,6 +236,7 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     d.bucket_start = m->bucket_start;
     d.geo = m->geo;
     d.geo_stride = gstride;
+    d.geo_rows = (long long)nd * gstride;
     d.interleave = m->tune.interleave;
     d.ncell = m->ncell;
     d.nx = m->nx; d.ny = m->ny; d.nz = m->nz; d.nb = m->nb;
@@ -384,7 +390,7 @@ int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out)
 int art_destroy_mesh(art_mesh *m)
 {
     if (!m) return ART_OK;
-    void *bufs[] = {m->fields, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
+    void *bufs[] = {m->fields, m->fields_t, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
                     m->state, m->geo, m->acc, m->items, m->desc, m->seg_count};
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
@@ -406,6 +412,7 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
         hipStream_t st = (hipStream_t)hip_stream;
         const size_t n = (size_t)m->ncell * nbins;
         if ((rc = dev_alloc(&m->fields, n, &m->fields_cap))) return rc;
+        if ((rc = dev_alloc(&m->fields_t, n, &m->fields_t_cap))) return rc;
         if ((rc = dev_alloc(&m->bad, 1, &m->bad_cap))) return rc;
         const float *dk = kappa, *ds = S;
         if (!on_device) {
@@ -416,7 +423,7 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
             ds = m->stage + n;
         }
         HIPCHK(hipMemsetAsync(m->bad, 0, sizeof(int), st));
-        HIPCHK(art_launch_layout(dk, ds, m->ncell, nbins, m->h, m->fields, m->bad, st));
+        HIPCHK(art_launch_layout(dk, ds, m->nx, m->ny, m->nz, nbins, m->h, m->fields, m->fields_t, m->bad, st));
         int bad = 0;
         HIPCHK(hipMemcpyAsync(&bad, m->bad, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

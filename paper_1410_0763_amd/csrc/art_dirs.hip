@@ -223,8 +223,10 @@ __global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__
             s1 = 1.0f; s2 = 0.0f; s3 = 0.0f;
         }
         const unsigned npos = (s1 > 0.f) + (s2 > 0.f) + (s3 > 0.f);
-        const unsigned code = (unsigned)(shb + 1) | ((unsigned)(shc + 1) << 2) |
-                              ((unsigned)b_first << 4) | (npos << 5);
+        // moves in slab order: 0 none, 1 a b-plane, 2 a c-plane
+        const unsigned mv1 = shb && (b_first || !shc) ? 1u : (shc ? 2u : 0u);
+        const unsigned mv2 = shb && shc ? (b_first ? 2u : 1u) : 0u;
+        const unsigned code = mv1 | (mv2 << 2) | (npos << 5);
         geo[(long long)d * stride + i] =
             make_uint4(__float_as_uint(s1), __float_as_uint(s2), __float_as_uint(s3), code);
     }

@@ -1,8 +1,10 @@
 // art_fields.hip -- field layout, normalisation / rates, exit sums.
 //
 // Layout (at set_fields): kappa and S arrive as [bin][cell]; the march wants
-// all bins of a cell in one place, so each cell gets nb float4 records
-// {kappa h, 1/(kappa h), S, 0} (kappa h is the optical depth per cell length).
+// all bins of a cell in one place, so each cell gets nb float2 records
+// {kappa h, S} (kappa h is the optical depth per cell length), once with cells
+// x fastest and once with y fastest, then z, then x (read by the directions
+// whose dominant axis is x, whose tiles span y and z).
 //
 // Normalisation (Sect. 2.2, eq mean_intensity, and eq gamma_diff):
 //   J_in = A1 / N_d,  J = J_in + S,  J_exact = J_in + S A2 / N_d,
@@ -24,17 +26,22 @@ namespace {
 __global__ __launch_bounds__(256) void art_layout_kernel(const float *__restrict__ kappa,
                                                          const float *__restrict__ S,
                                                          long long ncell, int nb, float h,
-                                                         float4 *__restrict__ fields,
+                                                         int nx, int ny, int nz,
+                                                         float2 *__restrict__ fields,
+                                                         float2 *__restrict__ fields_t,
                                                          int *__restrict__ bad)
 {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
+    const long long x = c % nx, y = (c / nx) % ny, z = c / ((long long)nx * ny);
+    const long long ct = (x * nz + z) * ny + y;           // y fastest, then z, then x
     for (int b = 0; b < nb; ++b) {
         const float k = kappa[(long long)b * ncell + c];
         const float s = S[(long long)b * ncell + c];
         if (!(k >= 0.0f) || !isfinite(k) || !isfinite(s)) *bad = 1;
         const float kh = k * h;
-        fields[c * nb + b] = make_float4(kh, kh > 0.0f ? 1.0f / kh : INFINITY, s, 0.0f);
+        fields[c * nb + b] = make_float2(kh, s);
+        fields_t[ct * nb + b] = make_float2(kh, s);
     }
 }
 
@@ -51,7 +58,7 @@ struct GW {
 
 __global__ __launch_bounds__(256) void art_normalize_kernel(
     const float *__restrict__ acc, const int *__restrict__ bucket_start, int nbuckets,
-    const float4 *__restrict__ fields, long long ncell, int nb, float inv_nd, GW gw,
+    const float2 *__restrict__ fields, long long ncell, int nb, float inv_nd, GW gw,
     float *__restrict__ J_in, float *__restrict__ J, float *__restrict__ J_exact,
     float *__restrict__ Gamma, float *__restrict__ A1raw, float *__restrict__ A2raw)
 {
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(256) void art_normalize_kernel(
         const long long bc = (long long)b * ncell + c;
         if (A1raw) A1raw[bc] = a1;
         if (A2raw) A2raw[bc] = a2;
-        const float s = fields[c * nb + b].z;
+        const float s = fields[c * nb + b].y;
         const float jin = a1 * inv_nd;
         if (J_in) J_in[bc] = jin;
         if (J) J[bc] = jin + s;
@@ -122,12 +129,14 @@ __global__ __launch_bounds__(256) void art_exit_sum_kernel(const ArtDir *__restr
 
 }  // namespace
 
-hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
-                             double h, float4 *fields, int *bad_flag, hipStream_t stream)
+hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny, int nz, int nb,
+                             double h, float2 *fields, float2 *fields_t, int *bad_flag,
+                             hipStream_t stream)
 {
+    const long long ncell = (long long)nx * ny * nz;
     const long long nblk = (ncell + 255) / 256;
     hipLaunchKernelGGL(art_layout_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, kappa, S,
-                       ncell, nb, (float)h, fields, bad_flag);
+                       ncell, nb, (float)h, nx, ny, nz, fields, fields_t, bad_flag);
     return hipGetLastError();
 }
 
@@ -140,7 +149,7 @@ hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream)
 }
 
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
-                                const float4 *fields, long long ncell, int nb, int nd,
+                                const float2 *fields, long long ncell, int nb, int nd,
                                 const float *gw4, float *J_in, float *J, float *J_exact,
                                 float *Gamma, float *A1raw, float *A2raw, hipStream_t stream)
 {

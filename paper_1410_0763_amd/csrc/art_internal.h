@@ -28,7 +28,8 @@ struct ArtDir {
 
 // Everything one workgroup of the march needs about its mesh.
 struct ArtMeshDesc {
-    const float4 *fields;      // [cell][nb] = {kappa h, 1/(kappa h), S, 0}
+    const float2 *fields;      // [cell][nb] = {kappa h, S}, cells x fastest
+    const float2 *fields_t;    // the same with y fastest, then z, then x
     float *state;              // ray intensities handed from block to block
     float *acc;                // [bucket][nb][2][cell] per-bucket direction sums
     const ArtDir *dirs;        // [N_d]
@@ -37,6 +38,7 @@ struct ArtMeshDesc {
     const uint4 *geo;          // [N_d][geo_stride] slab crossing table
     long long ncell;
     int geo_stride;            // max(nx, ny, nz)
+    long long geo_rows;        // rows of the crossing table (N_d * geo_stride)
     int interleave;            // directions marched together by one wave (1, 2, 4)
     int nx, ny, nz, nb;
     int depth;                 // block cells along the dominant axis
@@ -62,10 +64,11 @@ hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begi
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,
                             hipStream_t stream);
-hipError_t art_launch_layout(const float *kappa, const float *S, long long ncell, int nb,
-                             double h, float4 *fields, int *bad_flag, hipStream_t stream);
+hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny, int nz, int nb,
+                             double h, float2 *fields, float2 *fields_t, int *bad_flag,
+                             hipStream_t stream);
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
-                                const float4 *fields, long long ncell, int nb, int nd,
+                                const float2 *fields, long long ncell, int nb, int nd,
                                 const float *gw4, float *J_in, float *J, float *J_exact,
                                 float *Gamma, float *A1raw, float *A2raw, hipStream_t stream);
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
@@ -78,7 +81,7 @@ int art_march_max_lds_bytes();
 int art_march_lds_floats(int depth, int nb);
 // Shape, bins, cell size and device field records ([cell][nb] {kappa h,
 // 1/(kappa h), S, 0}; NULL before art_set_fields) of a mesh.
-void art_mesh_fields(const art_mesh *mesh, int dims[3], int *nb, double *h, const float4 **fields);
+void art_mesh_fields(const art_mesh *mesh, int dims[3], int *nb, double *h, const float2 **fields);
 
 // float -> bfloat16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t art_bf16_rne(float f)

@@ -15,57 +15,66 @@
 // that copy, so no global atomics are needed (the single-writer property that
 // Sect. 3.1 obtains with ray groups).
 //
-// Slab sweep.  Lane (col, row) of a wave owns column (lo_b + col, lo_c + row).
-// Ray (j,k) sits at transverse position (j + 1/2 + t_b s, k + 1/2 + t_c s) at
+// Slab sweep.  Each lane of a wave owns one column of the 8 x 8 tile.  Ray
+// (j,k) sits at transverse position (j + 1/2 + t_b s, k + 1/2 + t_c s) at
 // depth s, so at the top of slab i it is in column (j + B_b(i), k + B_c(i)),
 // B(i) = floor(1/2 + t i): the lattice shift is the same for every ray.  Hence
 // the whole wave shares one segment pattern per slab: at most one b- and one
 // c-plane crossing, splitting the slab into up to three segments.  At a
-// crossing every ray moves to the neighbouring column, i.e. the intensities
-// move one lane over (DPP row shift along b, ds_bpermute along c); edge lanes
-// hand rays to and from the neighbouring blocks through the state buffer.  A
-// lane reads its own cell's fields once per slab and adds its contributions to
-// its own cell once per slab.  The per-(direction, slab) pattern comes from a
-// table built once per sweep and is read with scalar loads, so every branch on
-// it is a scalar branch (its segment lengths stay in vector registers).
+// crossing every ray moves to the neighbouring column.  All directions of a
+// bucket travel the same way along b and c, so the lane-to-column map is
+// mirrored per bucket such that a move always hands lane l - 1's ray to lane
+// l along b (a DPP row shift) and lane l - 8's ray along c (ds_bpermute); edge
+// lanes hand rays to and from the neighbouring blocks through the state
+// buffer.  A lane reads its own cell's fields once per slab and adds its
+// contributions to its own cell once per slab.  The per-(direction, slab)
+// pattern comes from a table built once per sweep (segment lengths and a code
+// word naming the moves in order); the code word goes to a scalar register, so
+// every branch on it is a scalar branch.
 //
 // A wave marches K directions at once and orders a slab's work by phase: the
-// first segment of every direction, then the first crossing and second
-// segment of every direction, then the second crossing and third segment.
-// The rays that enter the tile during the slab are loaded at its top and are
-// first needed after the K first segments; the next slab's fields are loaded
-// one slab ahead.
+// first segment of every direction; the first move of every direction, then
+// their second segments; the second moves, then the third segments.  The rays
+// that enter the tile during the slab are loaded at its top and are first
+// needed after the K first segments; the next slab's fields are loaded one
+// slab ahead, the table two slabs ahead.
 //
 // Memory is addressed through buffer descriptors with 32-bit byte offsets
-// (wave-uniform bases in scalar registers): a direction's state region, and
-// the block's field records.  A lane that must not store (it is not at the
-// tile edge the rays leave through, or outside the mesh) stores to an offset
-// beyond the descriptor's range, which the hardware drops.  Each direction's
-// state region starts with a boundary slot holding I_bc, read by every lane
-// whose ray enters through a mesh face (and by lanes that need no ray).
+// (wave-uniform bases in scalar registers): the bucket's state region, the
+// block's field records and the table.  A lane that must not store (it is not
+// at the tile edge the rays leave through, or outside the mesh) stores to an
+// offset beyond the descriptor's range, which the hardware drops; a load there
+// returns 0 without touching memory.  Each direction's state region starts
+// with a boundary slot holding I_bc, read by every lane whose ray enters
+// through a mesh face; with I_bc = 0 those lanes, and lanes that need no ray
+// in a slab, read out of range instead.
+//
+// Field records are {kappa h, S} per (cell, bin), 8 bytes, all bins of a cell
+// together; directions whose dominant axis is x read a second copy with y
+// fastest, so that for every axis the lanes of a tile row read consecutive
+// records.  |n_a| / (kappa h) comes from v_rcp_f32 once per slab and bin.
 //
 // Per segment of depth length ds (path length dL = ds / |n_a| cells), per bin
 // (eq rt and eq path_averaged_intensity):
-//   x = kappa h dL,  e1 = 1 - e^{-x},  phi = e1 / x,
+//   x = kappa h dL,  phi = (1 - e^{-x}) / x,
 //   A1 += ds * I * phi        (sum_j dtau_j Ibar_in,j / sum_j dtau_j per direction)
 //   A2 += ds * (1 - phi)      (exact path average of the source term)
-//   I  <- I + (S - I) e1      (= I e^{-x} + S (1 - e^{-x}))
-// For x < 1/8, e1, phi and 1 - phi come from the Taylor series of
-// (x - 1 + e^{-x}) / x^2 so that none of them cancels; above, from v_exp_f32.
-// Slab geometry is double precision; transfer is single precision.
+//   I  <- I + (S - I) x phi   (= I e^{-x} + S (1 - e^{-x}))
+// For x >= 1/8, phi ds = (1 - e^{-x}) |n_a| / (kappa h) with e^{-x} from
+// v_exp_f32; for x < 1/8, (1 - phi) ds = x q(x) ds from the series of
+// q(x) = (x - 1 + e^{-x}) / x^2 to third order (relative truncation below
+// 7e-7), so that neither phi nor 1 - phi cancels.  In both branches
+// x phi = (phi ds) (kappa h / |n_a|).  Slab geometry is double precision;
+// transfer is single precision.
 #include "art_internal.h"
-
-#define ART_LOG2E 1.4426950408889634f
 
 namespace {
 
-typedef float v3f __attribute__((ext_vector_type(3)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef __attribute__((address_space(1))) float g_f;
-typedef __attribute__((address_space(1))) const u32x4 g_u4;
 typedef __attribute__((address_space(4))) const ArtDir c_dir;
 typedef __attribute__((address_space(4))) const int c_int;
 
@@ -118,12 +127,27 @@ __device__ __forceinline__ void store_slot(rsrc_t r, unsigned off, const float *
     }
 }
 
-// Field record {kappa h, 1/(kappa h), S} of one (cell, bin): 12 bytes of a
-// 16-byte record (a dead fourth register would be reused at once and force a
-// wait for the whole load).
-__device__ __forceinline__ v3f load_field(rsrc_t r, unsigned voff, unsigned soff)
+// Field records {kappa h, S} of all NB bins of one cell (8 bytes per bin,
+// two bins per 16-byte load).
+template <int NB>
+__device__ __forceinline__ void load_fields(rsrc_t r, unsigned voff, unsigned soff, float *kh, float *S)
 {
-    return __builtin_bit_cast(v3f, __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0));
+    if constexpr (NB == 1) {
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        kh[0] = __uint_as_float(a.x); S[0] = __uint_as_float(a.y);
+    } else {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        kh[0] = __uint_as_float(a.x); S[0] = __uint_as_float(a.y);
+        kh[1] = __uint_as_float(a.z); S[1] = __uint_as_float(a.w);
+        if constexpr (NB == 3) {
+            const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, voff + 16, soff, 0);
+            kh[2] = __uint_as_float(b.x); S[2] = __uint_as_float(b.y);
+        } else if constexpr (NB == 4) {
+            const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+            kh[2] = __uint_as_float(b.x); S[2] = __uint_as_float(b.y);
+            kh[3] = __uint_as_float(b.z); S[3] = __uint_as_float(b.w);
+        }
+    }
 }
 
 // A wave-uniform value kept in a vector register: per-direction constants
@@ -147,54 +171,39 @@ __device__ __forceinline__ void lds_add(float *p, float v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Value of `v` in lane `src` of the wave (src in [0, 64)); all lanes active.
-__device__ __forceinline__ float lane_get(float v, int src)
-{
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
-}
+// Small-x series in y = -x log2(e): x q(x) = y R(y) with
+// q(x) = (x - 1 + e^{-x}) / x^2 = 1/2 - x/6 + x^2/24 - x^3/120 + O(x^4) and
+// R(y) = sum_k c_k (-1)^(k+1) ln2^(k+1) y^k (c_k the coefficients of q).
+#define ART_LN2 0.69314718055994531
+#define ART_R0 ((float)(-0.5 * ART_LN2))
+#define ART_R1 ((float)(-(1.0 / 6.0) * ART_LN2 * ART_LN2))
+#define ART_R2 ((float)(-(1.0 / 24.0) * ART_LN2 * ART_LN2 * ART_LN2))
+#define ART_R3 ((float)(-(1.0 / 120.0) * ART_LN2 * ART_LN2 * ART_LN2 * ART_LN2))
+#define ART_YSMALL ((float)(-0.125 / ART_LN2))   // x < 1/8
 
-// Lane shift along b by one column (within each row of 8): row_shr:1 /
-// row_shl:1 of DPP move a value from the lane before / after; the lanes of
-// column 0 / 7, whose value comes from outside the row, are overwritten by
-// the caller.
-__device__ __forceinline__ float shift_prev(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float shift_next(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
-}
-
-// One segment of depth length ds in the lane's cell, for every bin; fw[b] is
-// |n_a| / (kappa_b h) of the cell.
 template <int NB>
-__device__ __forceinline__ void segment(const v3f *F, const float *fw, float ds, float invw,
-                                        float *I, float *a1, float *a2)
+__device__ __forceinline__ void segment(const float *Sv, const float *fw, const float *ifw,
+                                        const float *ify, float ds, float *I, float *a1, float *a2)
 {
-    const float dl = ds * invw;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const float x = F[b].x * dl;
+        const float y = ify[b] * ds;                     // -x log2(e)
         // large-x branch
-        const float e = __builtin_amdgcn_exp2f(-x * ART_LOG2E);
-        const float e1l = 1.0f - e;
+        const float e1l = 1.0f - __builtin_amdgcn_exp2f(y);
         const float lphil = e1l * fw[b];
         const float lpsil = ds - lphil;
-        // small-x branch: q = (x - 1 + e^{-x}) / x^2
-        const float qq = fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 720.0f, -1.0f / 120.0f),
-                                              1.0f / 24.0f), -1.0f / 6.0f), 0.5f);
-        const float xq = x * qq;
-        const float lpsis = ds * xq;
+        // small-x branch (truncation below 7e-7 relative for x < 1/8)
+        const float r = fmaf(y, fmaf(y, fmaf(y, ART_R3, ART_R2), ART_R1), ART_R0);
+        const float lpsis = ds * (y * r);
         const float lphis = ds - lpsis;
-        const float e1s = fmaf(-x, xq, x);
-        const bool small = x < 0.125f;
-        const float e1 = small ? e1s : e1l;
+        const bool small = y > ART_YSMALL;
         const float lphi = small ? lphis : lphil;
         const float lpsi = small ? lpsis : lpsil;
+        // 1 - e^{-x} = x phi = (phi ds) (kappa h / |n_a|) in either branch
+        const float e1 = lphi * ifw[b];
         a1[b] = fmaf(I[b], lphi, a1[b]);
         a2[b] += lpsi;
-        I[b] = fmaf(F[b].z - I[b], e1, I[b]);
+        I[b] = fmaf(Sv[b] - I[b], e1, I[b]);
     }
 }
 
@@ -204,11 +213,13 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
                                                         unsigned int *__restrict__ seg_count)
 {
     extern __shared__ __align__(16) float lds[];
-    const ArtItem it = items[blockIdx.x];
-    const ArtMeshDesc &M = meshes[it.mesh];
+    const int it_mesh = __builtin_amdgcn_readfirstlane(items[blockIdx.x].mesh);
+    const int it_block = __builtin_amdgcn_readfirstlane(items[blockIdx.x].block);
+    const int it_bucket = __builtin_amdgcn_readfirstlane(items[blockIdx.x].bucket);
+    const ArtMeshDesc &M = meshes[it_mesh];
     // (read through a generic pointer, which the compiler cannot prove uniform)
-    const int dbeg = __builtin_amdgcn_readfirstlane(M.bucket_start[it.bucket]);
-    const int dend = __builtin_amdgcn_readfirstlane(M.bucket_start[it.bucket + 1]);
+    const int dbeg = __builtin_amdgcn_readfirstlane(M.bucket_start[it_bucket]);
+    const int dend = __builtin_amdgcn_readfirstlane(M.bucket_start[it_bucket + 1]);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -217,15 +228,15 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
         return;
     }
     const int subsets = M.subsets;
-    const int cls = it.bucket / (8 * subsets);            // dominant axis of the bucket
-    const int oct = (it.bucket / subsets) % 8;
+    const int cls = it_bucket / (8 * subsets);            // dominant axis of the bucket
+    const int oct = (it_bucket / subsets) % 8;
     const int ab = cls == 0 ? 1 : 0, ac = cls == 2 ? 1 : 2;
     const int Na = cls == 0 ? M.nx : (cls == 1 ? M.ny : M.nz);
     const int Nb = ab == 0 ? M.nx : M.ny;
     const int Nc = ac == 1 ? M.ny : M.nz;
     const int depth = M.depth;
     const int nbb = (Nb + 7) / 8, nbc = (Nc + 7) / 8;
-    const int pb = it.block % nbb, pc = (it.block / nbb) % nbc, pa = it.block / (nbb * nbc);
+    const int pb = it_block % nbb, pc = (it_block / nbb) % nbc, pa = it_block / (nbb * nbc);
     const int lo_b = pb * 8, lo_c = pc * 8, lo_a = pa * depth;
     const int hi_a = min(lo_a + depth, Na);
     const int sig_neg = (oct >> cls) & 1;                 // rays travel towards -x_a
@@ -237,23 +248,28 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const long long sb = ab == 0 ? 1 : M.nx;
     const long long sc = ac == 1 ? M.nx : (long long)M.nx * M.ny;
 
-    const int col = lane & 7, row = lane >> 3;
-    const int gb = lo_b + col, gc = lo_c + row;
-    const bool in_dom = gb < Nb && gc < Nc;
-    // All directions of the bucket share its octant, so along b the rays only
-    // ever move one way (sgb = +1 or -1, towards larger or smaller b), and so
-    // along c.  When all rays move one column (b) or row (c): the lane's ray
-    // leaves the tile or the mesh (store its state: Lb / Lc), the lane takes
-    // the neighbour lane's ray (Tb / Tc), or it loads a ray arriving from the
-    // next tile (Nb / Nc; otherwise a fresh ray enters the mesh with I_bc).
+    // All directions of the bucket share its octant, so along b every ray
+    // moves the same way (towards smaller b if bneg), and so along c.  Lane
+    // (cl, rw) owns tile column cl, or 7 - cl if bneg (row rw, or 7 - rw if
+    // cneg): a b-move then always hands the ray of lane cl - 1 to lane cl (DPP
+    // row shift), a c-move that of lane - 8 to the lane.  At a move the lane
+    // stores its ray if it leaves the tile or the mesh (Lb / Lc), takes the
+    // neighbour lane's ray (Tb / Tc), or loads a ray arriving from the
+    // neighbouring tile (Nb / Nc; otherwise a ray entering the mesh, I_bc).
+    const int cl = lane & 7, rw = lane >> 3;
     const bool bneg = (oct >> ab) & 1, cneg = (oct >> ac) & 1;
-    const bool Lb = in_dom && (bneg ? col == 0 : (col == 7 || gb + 1 >= Nb));
-    const bool Tb = bneg ? (col <= 6 && gb + 1 < Nb) : col >= 1;
-    const bool Nb_ = in_dom && (bneg ? (col == 7 && gb + 1 < Nb) : (col == 0 && gb >= 1));
-    const bool Lc = in_dom && (cneg ? row == 0 : (row == 7 || gc + 1 >= Nc));
-    const bool Tc = cneg ? (row <= 6 && gc + 1 < Nc) : row >= 1;
-    const bool Nc_ = in_dom && (cneg ? (row == 7 && gc + 1 < Nc) : (row == 0 && gc >= 1));
-    const int csrc = (min(7, max(0, row + (cneg ? 1 : -1))) << 3) + col;   // lane a c-move takes from
+    const int gb = lo_b + (bneg ? 7 - cl : cl), gc = lo_c + (cneg ? 7 - rw : rw);
+    const bool in_dom = gb < Nb && gc < Nc;
+    const int gbs = bneg ? gb + 1 : gb - 1;               // column a b-move brings a ray from
+    const int gcs = cneg ? gc + 1 : gc - 1;
+    const bool Lb = in_dom && (cl == 7 || (bneg ? gb == 0 : gb + 1 >= Nb));
+    const bool Tb = cl >= 1 && gbs < Nb;
+    const bool Nb_ = in_dom && cl == 0 && gbs >= 0 && gbs < Nb;
+    const bool Lc = in_dom && (rw == 7 || (cneg ? gc == 0 : gc + 1 >= Nc));
+    const bool Tc = rw >= 1 && gcs < Nc;
+    const bool Nc_ = in_dom && rw == 0 && gcs >= 0 && gcs < Nc;
+    const int csrc4 = (rw >= 1 ? lane - 8 : lane) << 2;   // ds_bpermute byte address
+    const int dB = (bneg ? -1 : 1) * NB * 4;              // state offset change of a b-move
 
     // LDS accumulators: per cell of the block, {A1, A2} of every bin.
     const int V = depth * 64;                             // cells of one block
@@ -263,16 +279,23 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 
     // Field records of the block: base at its lowest cell, lane offset fixed,
     // slab offset in the scalar offset.
-    const long long base_cell = (long long)lo_a * sa + (long long)lo_b * sb + (long long)lo_c * sc;
-    const long long rec_left = (M.ncell - base_cell) * NB * 16;
-    const rsrc_t rF = make_rsrc((const float4 *)M.fields + base_cell * NB,
-                                (unsigned)min(rec_left, 0x7fffffffll));
-    const unsigned foff = in_dom ? (unsigned)((col * sb + row * sc) * NB * 16) : 0u;
+    // (x-dominant directions read the y-fastest copy, so that the lanes of a
+    // tile row read consecutive cells as for the other two axes)
+    const float2 *fbase = cls == 0 ? M.fields_t : M.fields;
+    const long long fsa = cls == 0 ? (long long)M.ny * M.nz : sa;
+    const long long fsb = cls == 0 ? 1 : sb;
+    const long long fsc = cls == 0 ? M.ny : sc;
+    const long long base_cell = (long long)lo_a * fsa + (long long)lo_b * fsb + (long long)lo_c * fsc;
+    const long long rec_left = (M.ncell - base_cell) * NB * 8;
+    const rsrc_t rF = make_rsrc(fbase + base_cell * NB, (unsigned)min(rec_left, 0x7fffffffll));
+    const unsigned foff = in_dom ? (unsigned)(((gb - lo_b) * fsb + (gc - lo_c) * fsc) * NB * 8) : 0u;
     auto slab_soff = [&](int t) {     // byte offset of the t-th slab swept
         const int la = sig_neg ? nslab - 1 - t : t;
-        return (unsigned)(la * sa * NB * 16);
+        return (unsigned)(la * fsa * NB * 8);
     };
-    g_u4 *geo = (g_u4 *)M.geo;
+    // crossing table: one descriptor over all of it (rows past a direction's
+    // last slab are read but never used; past the table they read 0)
+    const rsrc_t rG = make_rsrc(M.geo, (unsigned)min((long long)M.geo_rows * 16, 0x7fffffffll));
     c_dir *dirs = (c_dir *)M.dirs;
     c_int *order = (c_int *)M.order;
     const int gstride = M.geo_stride;
@@ -283,14 +306,15 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const rsrc_t rS = make_rsrc(M.state + sbase,
                                 (unsigned)((Dl.state_off + (long long)Dl.nj * Dl.nk * NB - sbase) * 4));
     unsigned int sseg = 0;   // segments of positive length per in-mesh lane (wave-uniform)
+    const bool zero_bc = M.I_bc == 0.0f;
 
     for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
         bool act[K];
-        int gbase[K];
-        unsigned cstride[K];    // bytes between rays of neighbouring c (nj slots)
+        unsigned gvoff[K];      // byte offset of the direction's first table row
+        unsigned dC[K];         // state offset change of a c-move
         unsigned dbase[K];      // byte offset of the direction's boundary slot in rS
         unsigned cur[K];        // byte offset of the lane's current ray in rS
-        float invw[K], wdir[K];
+        float invw[K], invwl[K], wdir[K];
         float I[K][NB];
         float ib[K][NB], ic[K][NB];   // rays entering the tile during the current slab
         u32x4 gcur[K], gnext[K];      // crossing table entries of the current and next slab
@@ -304,31 +328,34 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             const double tc = ac == 1 ? D.beta[1] : D.beta[2];
             const int Bb = (int)floor(fma(tb, (double)d0, 0.5));
             const int Bc = (int)floor(fma(tc, (double)d0, 0.5));
-            gbase[m] = d * gstride;
+            gvoff[m] = in_vgpr((unsigned)(d * gstride * 16));
             const unsigned db = (unsigned)((D.state_off - NB - sbase) * 4);
             cur[m] = db + (unsigned)((1 + (gc - Bc - D.k0) * D.nj + (gb - Bb - D.j0)) * NB * 4);
-            cstride[m] = in_vgpr((unsigned)(D.nj * NB * 4));
-            dbase[m] = in_vgpr(db);
+            dC[m] = in_vgpr((unsigned)((cneg ? -1 : 1) * D.nj * NB * 4));
+            // boundary slot (I_bc); with I_bc = 0 an out-of-range offset, which
+            // reads 0 without touching memory
+            dbase[m] = in_vgpr(zero_bc ? ART_OOB : db);
             invw[m] = in_vgpr((float)D.invw);
+            invwl[m] = in_vgpr((float)(-D.invw * 1.4426950408889634));
             wdir[m] = in_vgpr((float)D.w);
             // rays entering through the top face come from the block above
             load_slot<NB>(rS, (in_dom && d0 > 0) ? cur[m] : dbase[m], I[m]);
-            gcur[m] = geo[gbase[m] + d0];
-            gnext[m] = geo[gbase[m] + min(d0 + 1, Na - 1)];
+            gcur[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)(d0 * 16), 0);
+            gnext[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((d0 + 1) * 16), 0);
         }
-        v3f F[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) F[b] = load_field(rF, foff + 16 * b, slab_soff(0));
+        float kh[NB], Sv[NB];
+        load_fields<NB>(rF, foff, slab_soff(0), kh, Sv);
 
         for (int t = 0; t < nslab; ++t) {
             const int i = d0 + t;
             // next slab's fields (past the last slab: a harmless repeat)
             const unsigned so_next = slab_soff(t + 1 < nslab ? t + 1 : t);
-            v3f Fn[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) Fn[b] = load_field(rF, foff + 16 * b, so_next);
+            float khn[NB], Svn[NB];
+            load_fields<NB>(rF, foff, so_next, khn, Svn);
             // the table entry is the same in every lane: its code word goes to a
-            // scalar register, so that every branch on it is a scalar branch
+            // scalar register, so that every branch on it is a scalar branch.
+            // Code: bits 0-1 first move (0 none, 1 b, 2 c), bits 2-3 second
+            // move, bits 5+ segments of positive length.
             unsigned codes[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) codes[m] = __builtin_amdgcn_readfirstlane(gcur[m].w);
@@ -336,43 +363,54 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             u32x4 gnext2[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const unsigned code = codes[m];
-                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
-                const bool b_first = (code >> 4) & 1u;
-                const int dB = shb * NB * 4;
-                const int dC = shc * (int)cstride[m];
-                load_slot<NB>(rS, (shb && Nb_) ? cur[m] - (b_first ? 0 : dC) - dB : dbase[m], ib[m]);
-                load_slot<NB>(rS, (shc && Nc_) ? cur[m] - (b_first ? dB : 0) - dC : dbase[m], ic[m]);
-                gnext2[m] = geo[gbase[m] + min(i + 2, Na - 1)];
+                const unsigned c1 = codes[m] & 3u, c2 = (codes[m] >> 2) & 3u;
+                const bool hb = c1 == 1u || c2 == 1u, hc = c1 == 2u || c2 == 2u;
+                const unsigned ob = cur[m] - (unsigned)dB - (c1 == 2u ? dC[m] : 0u);
+                const unsigned oc = cur[m] - dC[m] - (c1 == 1u ? (unsigned)dB : 0u);
+                load_slot<NB>(rS, (hb && Nb_) ? ob : dbase[m], ib[m]);
+                load_slot<NB>(rS, (hc && Nc_) ? oc : dbase[m], ic[m]);
+                gnext2[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((i + 2) * 16), 0);
             }
-            float fw[K][NB];
+            // |n_a| / (kappa h) per direction and bin (1/0 = inf: vacuum takes the
+            // small-x branch, which does not use it)
+            float rk[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) rk[b] = __builtin_amdgcn_rcpf(kh[b]);
+            // |n_a| / (kappa h), its inverse, and -log2(e) kappa h / |n_a|
+            float fw[K][NB], ifw[K][NB], ify[K][NB];
 #pragma unroll
             for (int m = 0; m < K; ++m)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) fw[m][b] = F[b].y * wdir[m];
+                for (int b = 0; b < NB; ++b) {
+                    fw[m][b] = rk[b] * wdir[m];
+                    ifw[m][b] = kh[b] * invw[m];
+                    ify[m][b] = kh[b] * invwl[m];
+                }
             float a1[NB], a2[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) a1[b] = a2[b] = 0.0f;
 
-            // crossing of a b-plane: every ray moves from column gb to gb + shb
-            auto cross_b = [&](int m, int shb) {
+            // a b-move: every ray moves one column; lane cl takes lane cl - 1's ray
+            auto cross_b = [&](int m) {
                 store_slot<NB>(rS, Lb ? cur[m] : ART_OOB, I[m]);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const float moved = bneg ? shift_next(I[m][b]) : shift_prev(I[m][b]);
+                    const float moved =
+                        __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(I[m][b]), 0x111, 0xF, 0xF, true));
                     I[m][b] = Tb ? moved : ib[m][b];
                 }
-                cur[m] -= shb * NB * 4;
+                cur[m] -= (unsigned)dB;
             };
-            // crossing of a c-plane: every ray moves from row gc to gc + shc
-            auto cross_c = [&](int m, int shc) {
+            // a c-move: every ray moves one row; the lane takes lane - 8's ray
+            auto cross_c = [&](int m) {
                 store_slot<NB>(rS, Lc ? cur[m] : ART_OOB, I[m]);
+                float moved[NB];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const float moved = lane_get(I[m][b], csrc);
-                    I[m][b] = Tc ? moved : ic[m][b];
-                }
-                cur[m] -= shc * (int)cstride[m];
+                for (int b = 0; b < NB; ++b)
+                    moved[b] = __int_as_float(__builtin_amdgcn_ds_bpermute(csrc4, __float_as_int(I[m][b])));
+#pragma unroll
+                for (int b = 0; b < NB; ++b) I[m][b] = Tc ? moved[b] : ic[m][b];
+                cur[m] -= dC[m];
             };
 
             // phase 1: first segment of every direction
@@ -380,27 +418,31 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             for (int m = 0; m < K; ++m) {
                 if (!act[m]) continue;
                 sseg += codes[m] >> 5;
-                segment<NB>(F, fw[m], __uint_as_float(gcur[m].x), invw[m], I[m], a1, a2);
+                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].x), I[m], a1, a2);
             }
-            // phase 2: first crossing and second segment
+            // phase 2: first move of every direction, then its second segment
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const unsigned code = codes[m];
-                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
-                if (!act[m] || !(shb || shc)) continue;
-                const bool b_first = (code >> 4) & 1u;
-                if (shb && (b_first || !shc)) cross_b(m, shb); else cross_c(m, shc);
-                segment<NB>(F, fw[m], __uint_as_float(gcur[m].y), invw[m], I[m], a1, a2);
+                const unsigned c1 = codes[m] & 3u;
+                if (!act[m] || !c1) continue;
+                if (c1 == 1u) cross_b(m); else cross_c(m);
             }
-            // phase 3: second crossing and third segment
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const unsigned code = codes[m];
-                const int shb = (int)(code & 3u) - 1, shc = (int)((code >> 2) & 3u) - 1;
-                if (!act[m] || !(shb && shc)) continue;
-                const bool b_first = (code >> 4) & 1u;
-                if (b_first) cross_c(m, shc); else cross_b(m, shb);
-                segment<NB>(F, fw[m], __uint_as_float(gcur[m].z), invw[m], I[m], a1, a2);
+                if (!act[m] || !(codes[m] & 3u)) continue;
+                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].y), I[m], a1, a2);
+            }
+            // phase 3: second move and third segment
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const unsigned c2 = (codes[m] >> 2) & 3u;
+                if (!act[m] || !c2) continue;
+                if (c2 == 1u) cross_b(m); else cross_c(m);
+            }
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                if (!act[m] || !((codes[m] >> 2) & 3u)) continue;
+                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].z), I[m], a1, a2);
             }
 
             if (in_dom) {
@@ -422,7 +464,10 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
                 }
             }
 #pragma unroll
-            for (int b = 0; b < NB; ++b) F[b] = Fn[b];
+            for (int b = 0; b < NB; ++b) {
+                kh[b] = khn[b];
+                Sv[b] = Svn[b];
+            }
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 gcur[m] = gnext[m];
@@ -445,11 +490,12 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     if (threadIdx.x == 0) seg_count[blockIdx.x] = *wg_count;
 
     // Flush: this workgroup is the only writer of its block in this bucket's copy.
-    g_f *dst = (g_f *)M.acc + (long long)it.bucket * NB * 2 * M.ncell;
+    g_f *dst = (g_f *)M.acc + (long long)it_bucket * NB * 2 * M.ncell;
     for (int idx = threadIdx.x; idx < NB * 2 * V; idx += blockDim.x) {
-        const int comp = idx % (2 * NB), cl = idx / (2 * NB);
-        const int la = cl >> 6, l = cl & 63;
-        const int cb = lo_b + (l & 7), cc = lo_c + (l >> 3);
+        const int comp = idx % (2 * NB), cell = idx / (2 * NB);
+        const int la = cell >> 6, l = cell & 63;
+        const int cb = lo_b + (bneg ? 7 - (l & 7) : (l & 7));
+        const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
         if (la >= nslab || cb >= Nb || cc >= Nc) continue;
         const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
         dst[comp * M.ncell + wc] = accl[idx];

@@ -61,21 +61,21 @@ struct Stat3 {
 
 // Network input from the mesh's field records (bin 0 of nb) and J_coarse.
 __global__ __launch_bounds__(256) void features_rec_kernel(const float *__restrict__ J,
-                                                           const float4 *__restrict__ rec, int nb,
+                                                           const float2 *__restrict__ rec, int nb,
                                                            float inv_h, long long V, Stat3 mu,
                                                            Stat3 isd, uint16_t *__restrict__ x)
 {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const float4 r = rec[v * nb];
-    art_feature_store(J[v], r.x * inv_h, r.z, mu.a, isd.a, x + v * 16);
+    const float2 r = rec[v * nb];
+    art_feature_store(J[v], r.x * inv_h, r.y, mu.a, isd.a, x + v * 16);
 }
 
 // Outputs of an accepted prediction.
 __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ Js,
                                                      const float *__restrict__ Jc,
                                                      const float *__restrict__ Jexc,
-                                                     const float4 *__restrict__ rec, int nb,
+                                                     const float2 *__restrict__ rec, int nb,
                                                      float g0, long long V, float *__restrict__ J,
                                                      float *__restrict__ J_in,
                                                      float *__restrict__ J_exact,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ J
     if (v >= V) return;
     const float j = Js[v];
     if (J) J[v] = j;
-    if (J_in) J_in[v] = j - rec[v * nb].z;
+    if (J_in) J_in[v] = j - rec[v * nb].y;
     if (J_exact) J_exact[v] = j + (Jexc[v] - Jc[v]);
     if (Gamma) Gamma[v] = g0 * j;
 }
@@ -327,7 +327,7 @@ int forward(art_surrogate *s, const void *x, hipStream_t st)
     return ART_OK;
 }
 
-int check_mesh(const art_surrogate *s, const art_mesh *mesh, const float4 **rec, int *nb, double *h,
+int check_mesh(const art_surrogate *s, const art_mesh *mesh, const float2 **rec, int *nb, double *h,
                const char *who)
 {
     int dims[3];
@@ -517,7 +517,7 @@ int art_surrogate_make_pair(art_surrogate *s, art_mesh *mesh, int nside_coarse, 
 {
     if (!s || !mesh || !target || !J_coarse || !(lambda >= 0.0f))
         return sg_fail(ART_E_INVAL, "art_surrogate_make_pair: bad arguments");
-    const float4 *rec;
+    const float2 *rec;
     int nb;
     double h;
     RCCHK(check_mesh(s, mesh, &rec, &nb, &h, "art_surrogate_make_pair"));
@@ -680,7 +680,7 @@ int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int 
     if (!mesh || !s || !out) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: NULL argument");
     if (out->exit_sum) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: exit sums are not produced");
     if (gamma_w && !std::isfinite(gamma_w[0])) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: gamma_w not finite");
-    const float4 *rec;
+    const float2 *rec;
     int nb;
     double h;
     RCCHK(check_mesh(s, mesh, &rec, &nb, &h, "art_sweep_surrogate"));
