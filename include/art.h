@@ -63,13 +63,13 @@ typedef struct {
  * cut into blocks of 8 x 8 columns (the two other axes) by `depth` cells
  * along a; one workgroup of `waves` 64-lane waves marches one block for one
  * bucket of directions (one of `subsets` parts of a dominant-axis x octant
- * group).  A new mesh starts with {depth 8, subsets 1, waves 1, interleave 4},
+ * group).  A new mesh starts with {depth 6, subsets 1, waves 1, interleave 3},
  * the fastest shape measured for a 256^3 mesh with 768 directions and 4 bins. */
 typedef struct {
     int depth;        /* cells of a block along the dominant axis, 1..256 */
     int subsets;      /* buckets per (dominant axis, octant) group, 1..64 */
     int waves;        /* waves per workgroup, 1..8 */
-    int interleave;   /* directions marched together by one wave: 1, 2 or 4 */
+    int interleave;   /* directions marched together by one wave: 1, 2, 3 or 4 */
 } art_tuning;
 
 /* Create a mesh of nx*ny*nz cubic cells of side cell_size (> 0).
@@ -120,8 +120,8 @@ int art_get_tuning(const art_mesh *mesh, art_tuning *t);
 
 /* Autotuner: for this mesh (fields set) and Nside, run a warm-up and a timed
  * sweep (HIP events around direction setup, march and normalisation) with
- * each candidate launch shape (candidates NULL: depth in {4, 6, 8, 12, 16} x
- * interleave in {2, 4}, one subset, one wave), keep the fastest on the mesh,
+ * each candidate launch shape (candidates NULL: depth in {4, 6, 8, 12} x
+ * interleave in {2, 3, 4}, one subset, one wave), keep the fastest on the mesh,
  * and return it in *best and its sweep time in *best_ms (either may be NULL).
  * Candidates the mesh cannot run (local-memory limit) are skipped; on error
  * the mesh keeps its previous tuning.  Synchronises hip_stream and holds a

@@ -67,7 +67,7 @@ struct art_mesh {
     double h = 1.0;
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
-    art_tuning tune{8, 1, 1, 4};
+    art_tuning tune{6, 1, 1, 3};
     int mbd = 0, mbd_key[2] = {-1, -1};   // largest bucket (directions) for (nside, subsets)
 
     float2 *fields = nullptr; size_t fields_cap = 0;
@@ -114,8 +114,8 @@ int validate_tuning(const art_tuning &t, int nb)
     if (t.depth < 1 || t.depth > 256) return fail(ART_E_INVAL, "tuning: depth must be in [1, 256]");
     if (t.subsets < 1 || t.subsets > 64) return fail(ART_E_INVAL, "tuning: subsets must be in [1, 64]");
     if (t.waves < 1 || t.waves > 8) return fail(ART_E_INVAL, "tuning: waves must be in [1, 8]");
-    if (t.interleave != 1 && t.interleave != 2 && t.interleave != 4)
-        return fail(ART_E_INVAL, "tuning: interleave must be 1, 2 or 4");
+    if (t.interleave < 1 || t.interleave > 4)
+        return fail(ART_E_INVAL, "tuning: interleave must be 1, 2, 3 or 4");
     const long long lds = (long long)art_march_lds_floats(t.depth, std::max(nb, 1)) * 4;
     if (lds > art_march_max_lds_bytes())
         return fail(ART_E_UNSUPPORTED, "tuning: block accumulators need " + std::to_string(lds) +
@@ -527,8 +527,8 @@ int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_
             if (ncand < 1) return fail(ART_E_INVAL, "autotune: ncand must be positive");
             list.assign(cand, cand + ncand);
         } else {
-            for (int depth : {4, 6, 8, 12, 16})
-                for (int k : {2, 4}) list.push_back(art_tuning{depth, 1, 1, k});
+            for (int depth : {4, 6, 8, 12})
+                for (int k : {2, 3, 4}) list.push_back(art_tuning{depth, 1, 1, k});
         }
         if ((rc = dev_alloc(&scratch, (size_t)m->ncell * m->nb, &cap))) return done(rc);
         const int nd = 12 * nside * nside;

@@ -39,7 +39,7 @@ struct ArtMeshDesc {
     long long ncell;
     int geo_stride;            // max(nx, ny, nz)
     long long geo_rows;        // rows of the crossing table (N_d * geo_stride)
-    int interleave;            // directions marched together by one wave (1, 2, 4)
+    int interleave;            // directions marched together by one wave (1..4)
     int nx, ny, nz, nb;
     int depth;                 // block cells along the dominant axis
     int subsets;               // buckets per (dominant axis, octant) group

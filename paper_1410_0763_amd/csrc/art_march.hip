@@ -36,8 +36,8 @@
 // first segment of every direction; the first move of every direction, then
 // their second segments; the second moves, then the third segments.  The rays
 // that enter the tile during the slab are loaded at its top and are first
-// needed after the K first segments; the next slab's fields are loaded one
-// slab ahead, the table two slabs ahead.
+// needed after the K first segments; the next slab's fields and table
+// entries are loaded one slab ahead.
 //
 // Memory is addressed through buffer descriptors with 32-bit byte offsets
 // (wave-uniform bases in scalar registers): the bucket's state region, the
@@ -182,12 +182,14 @@ __device__ __forceinline__ void lds_add(float *p, float v)
 #define ART_YSMALL ((float)(-0.125 / ART_LN2))   // x < 1/8
 
 template <int NB>
-__device__ __forceinline__ void segment(const float *Sv, const float *fw, const float *ifw,
-                                        const float *ify, float ds, float *I, float *a1, float *a2)
+__device__ __forceinline__ void segment(const float *kh, const float *Sv, const float *fw,
+                                        const float *ifw, float invwl, float ds, float *I,
+                                        float *a1, float *a2)
 {
+    const float dsl = ds * invwl;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const float y = ify[b] * ds;                     // -x log2(e)
+        const float y = kh[b] * dsl;                     // -x log2(e)
         // large-x branch
         const float e1l = 1.0f - __builtin_amdgcn_exp2f(y);
         const float lphil = e1l * fw[b];
@@ -341,7 +343,6 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             // rays entering through the top face come from the block above
             load_slot<NB>(rS, (in_dom && d0 > 0) ? cur[m] : dbase[m], I[m]);
             gcur[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)(d0 * 16), 0);
-            gnext[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((d0 + 1) * 16), 0);
         }
         float kh[NB], Sv[NB];
         load_fields<NB>(rF, foff, slab_soff(0), kh, Sv);
@@ -359,8 +360,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             unsigned codes[K];
 #pragma unroll
             for (int m = 0; m < K; ++m) codes[m] = __builtin_amdgcn_readfirstlane(gcur[m].w);
-            // rays entering the tile during this slab; the table two slabs ahead
-            u32x4 gnext2[K];
+            // rays entering the tile during this slab
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 const unsigned c1 = codes[m] & 3u, c2 = (codes[m] >> 2) & 3u;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
                 const unsigned oc = cur[m] - dC[m] - (c1 == 1u ? (unsigned)dB : 0u);
                 load_slot<NB>(rS, (hb && Nb_) ? ob : dbase[m], ib[m]);
                 load_slot<NB>(rS, (hc && Nc_) ? oc : dbase[m], ic[m]);
-                gnext2[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((i + 2) * 16), 0);
+                gnext[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((i + 1) * 16), 0);
             }
             // |n_a| / (kappa h) per direction and bin (1/0 = inf: vacuum takes the
             // small-x branch, which does not use it)
@@ -377,14 +377,13 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int b = 0; b < NB; ++b) rk[b] = __builtin_amdgcn_rcpf(kh[b]);
             // |n_a| / (kappa h), its inverse, and -log2(e) kappa h / |n_a|
-            float fw[K][NB], ifw[K][NB], ify[K][NB];
+            float fw[K][NB], ifw[K][NB];
 #pragma unroll
             for (int m = 0; m < K; ++m)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     fw[m][b] = rk[b] * wdir[m];
                     ifw[m][b] = kh[b] * invw[m];
-                    ify[m][b] = kh[b] * invwl[m];
                 }
             float a1[NB], a2[NB];
 #pragma unroll
@@ -418,7 +417,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             for (int m = 0; m < K; ++m) {
                 if (!act[m]) continue;
                 sseg += codes[m] >> 5;
-                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].x), I[m], a1, a2);
+                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].x), I[m], a1, a2);
             }
             // phase 2: first move of every direction, then its second segment
 #pragma unroll
@@ -430,7 +429,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m] || !(codes[m] & 3u)) continue;
-                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].y), I[m], a1, a2);
+                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].y), I[m], a1, a2);
             }
             // phase 3: second move and third segment
 #pragma unroll
@@ -442,7 +441,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m] || !((codes[m] >> 2) & 3u)) continue;
-                segment<NB>(Sv, fw[m], ifw[m], ify[m], __uint_as_float(gcur[m].z), I[m], a1, a2);
+                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].z), I[m], a1, a2);
             }
 
             if (in_dom) {
@@ -469,10 +468,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
                 Sv[b] = Svn[b];
             }
 #pragma unroll
-            for (int m = 0; m < K; ++m) {
-                gcur[m] = gnext[m];
-                gnext[m] = gnext2[m];
-            }
+            for (int m = 0; m < K; ++m) gcur[m] = gnext[m];
         }
         // rays leave through the block's far face (into the next block or out of the mesh)
 #pragma unroll
@@ -535,6 +531,7 @@ hipError_t launch_nb(const ArtItem *items, int nitems, const ArtMeshDesc *meshes
     case 1: return launch_nbk<NB, 1>(items, nitems, meshes, bytes, threads, seg_count, stream);
     case 2: return launch_nbk<NB, 2>(items, nitems, meshes, bytes, threads, seg_count, stream);
     case 4: return launch_nbk<NB, 4>(items, nitems, meshes, bytes, threads, seg_count, stream);
+    case 3: return launch_nbk<NB, 3>(items, nitems, meshes, bytes, threads, seg_count, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -97,7 +97,7 @@ def test_host_only_calls():
     assert L.art_get_tuning(h, ctypes.byref(t)) == 0
     assert t.depth > 0 and t.subsets > 0 and t.waves > 0
     for bad in (art.Tuning(32, 1, 0, 2), art.Tuning(0, 1, 8, 2), art.Tuning(300, 1, 8, 2),
-                art.Tuning(32, 65, 8, 2), art.Tuning(32, 1, 9, 2), art.Tuning(32, 1, 8, 3)):
+                art.Tuning(32, 65, 8, 2), art.Tuning(32, 1, 9, 2), art.Tuning(32, 1, 8, 5)):
         assert L.art_set_tuning(h, ctypes.byref(bad)) == -1
     ok = art.Tuning(16, 2, 4, 4)
     assert L.art_set_tuning(h, ctypes.byref(ok)) == 0
