@@ -90,6 +90,10 @@ __device__ void build_dir(int nside, int d, int nx, int ny, int nz, ArtDir *out)
     const int khi = (int)ceil((double)N[c] - 0.5 - fmin(0.0, tc * Na));
     D.j0 = jlo; D.nj = jhi - jlo + 1;
     D.k0 = klo; D.nk = khi - klo + 1;
+    // slot order: the lattice index that changes at the more frequent plane
+    // crossing runs fastest, so that the rays a tile hands over at that
+    // crossing (a tile edge along the other index) sit in consecutive slots
+    D.kfast = fabs(tb) > fabs(tc) ? 1 : 0;
     D.state_off = 0;
     D.bucket = -1;
     D.pad = 0;

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void art_exit_sum_kernel(const ArtDir *__restr
         const double N[3] = {(double)nx, (double)ny, (double)nz};
         const int nr = D.nj * D.nk;
         for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-            const int j = D.j0 + r % D.nj, k = D.k0 + r / D.nj;
+            const int j = D.j0 + (D.kfast ? r / D.nk : r % D.nj);
+            const int k = D.k0 + (D.kfast ? r % D.nk : r / D.nj);
             double lo = -INFINITY, hi = INFINITY;
             bool ok = true;
             for (int q = 0; q < 3; ++q) {

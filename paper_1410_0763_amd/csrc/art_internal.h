@@ -24,6 +24,8 @@ struct ArtDir {
     long long state_off;  // first float of this direction's ray states
     int bucket;           // (a * 8 + octant) * subsets + subset; -1 outside the range
     int pad;
+    int kfast;            // ray slots ordered k fastest (else j fastest)
+    int pad2;
 };
 
 // Everything one workgroup of the march needs about its mesh.

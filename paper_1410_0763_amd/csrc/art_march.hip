@@ -271,7 +271,6 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const bool Tc = rw >= 1 && gcs < Nc;
     const bool Nc_ = in_dom && rw == 0 && gcs >= 0 && gcs < Nc;
     const int csrc4 = (rw >= 1 ? lane - 8 : lane) << 2;   // ds_bpermute byte address
-    const int dB = (bneg ? -1 : 1) * NB * 4;              // state offset change of a b-move
 
     // LDS accumulators: per cell of the block, {A1, A2} of every bin.
     const int V = depth * 64;                             // cells of one block
@@ -313,7 +312,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
         bool act[K];
         unsigned gvoff[K];      // byte offset of the direction's first table row
-        unsigned dC[K];         // state offset change of a c-move
+        unsigned dB[K], dC[K];  // state offset change of a b-move, a c-move
         unsigned dbase[K];      // byte offset of the direction's boundary slot in rS
         unsigned cur[K];        // byte offset of the lane's current ray in rS
         float invw[K], invwl[K], wdir[K];
@@ -332,8 +331,10 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             const int Bc = (int)floor(fma(tc, (double)d0, 0.5));
             gvoff[m] = in_vgpr((unsigned)(d * gstride * 16));
             const unsigned db = (unsigned)((D.state_off - NB - sbase) * 4);
-            cur[m] = db + (unsigned)((1 + (gc - Bc - D.k0) * D.nj + (gb - Bb - D.j0)) * NB * 4);
-            dC[m] = in_vgpr((unsigned)((cneg ? -1 : 1) * D.nj * NB * 4));
+            const int sj = D.kfast ? D.nk : 1, sk = D.kfast ? 1 : D.nj;   // slot strides of j, k
+            cur[m] = db + (unsigned)((1 + (gc - Bc - D.k0) * sk + (gb - Bb - D.j0) * sj) * NB * 4);
+            dB[m] = in_vgpr((unsigned)((bneg ? -1 : 1) * sj * NB * 4));
+            dC[m] = in_vgpr((unsigned)((cneg ? -1 : 1) * sk * NB * 4));
             // boundary slot (I_bc); with I_bc = 0 an out-of-range offset, which
             // reads 0 without touching memory
             dbase[m] = in_vgpr(zero_bc ? ART_OOB : db);
@@ -365,8 +366,8 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             for (int m = 0; m < K; ++m) {
                 const unsigned c1 = codes[m] & 3u, c2 = (codes[m] >> 2) & 3u;
                 const bool hb = c1 == 1u || c2 == 1u, hc = c1 == 2u || c2 == 2u;
-                const unsigned ob = cur[m] - (unsigned)dB - (c1 == 2u ? dC[m] : 0u);
-                const unsigned oc = cur[m] - dC[m] - (c1 == 1u ? (unsigned)dB : 0u);
+                const unsigned ob = cur[m] - dB[m] - (c1 == 2u ? dC[m] : 0u);
+                const unsigned oc = cur[m] - dC[m] - (c1 == 1u ? dB[m] : 0u);
                 load_slot<NB>(rS, (hb && Nb_) ? ob : dbase[m], ib[m]);
                 load_slot<NB>(rS, (hc && Nc_) ? oc : dbase[m], ic[m]);
                 gnext[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((i + 1) * 16), 0);
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
                         __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(I[m][b]), 0x111, 0xF, 0xF, true));
                     I[m][b] = Tb ? moved : ib[m][b];
                 }
-                cur[m] -= (unsigned)dB;
+                cur[m] -= dB[m];
             };
             // a c-move: every ray moves one row; the lane takes lane - 8's ray
             auto cross_c = [&](int m) {
