@@ -57,6 +57,9 @@ typedef struct {
     float *Gamma;    /* sum_b gamma_w[b] (J_in_b + S_b): eq gamma_diff with its
                         frequency integral folded into the per-bin weights */
     float *exit_sum; /* per direction and bin: sum over rays of (I_exit - I_bc) */
+    float *Heat;     /* sum_b heat_in[b] J_in_b + heat_src[b] S_b: eq heat_diff with
+                        its frequency integrals folded into per-bin weights
+                        (art_set_heating; all 0 unless set) */
 } art_outputs;
 
 /* Launch shape of the sweep.  For directions with dominant axis a the mesh is
@@ -87,6 +90,18 @@ int art_destroy_mesh(art_mesh *mesh);
  * Synchronises hip_stream to report invalid values (ART_E_INVAL). */
 int art_set_fields(art_mesh *mesh, int nbins, const float *kappa, const float *S,
                    int on_device, void *hip_stream);
+
+/* Weights of the diffuse photo-heating rate (eq heat_diff, Sect. 2.2): the
+ * Heat output of later sweeps of this mesh (plain and batched; a batch takes
+ * the weights at art_batch_create) is sum_b heat_in[b] J_in_b +
+ * heat_src[b] S_b.  In the paper's monochromatic form, heat_in is
+ * 4 pi int sigma (1 - nu_0 / nu) dnu over the bin and heat_src the factor
+ * of the local recombination term (half the gamma_w of that term times
+ * h dnu_th); with a nonparametric spectrum of rectangular bins both are
+ * 4 pi int_bin sigma (1 - nu_i / nu) dnu.  heat_in, heat_src: host arrays
+ * [nbins] (NULL: all 0), finite.  ART_E_STATE before art_set_fields; a new
+ * bin count resets the weights to 0. */
+int art_set_heating(art_mesh *mesh, const float *heat_in, const float *heat_src);
 
 /* Full sweep over the 12 nside^2 HEALPix directions (Sect. 2.2-2.3).
  * gamma_w: host array [nbins] of rate weights (NULL = all 1).  I_bc: uniform

@@ -136,12 +136,13 @@ int art_surrogate_load(art_surrogate *s, const char *path, void *hip_stream);
 /* J of a sweep at nside_fine from the sweep at nside_coarse and the network,
  * for the field loaded in mesh (one bin, the surrogate's shape, I_bc = 0).
  * If the gate accepts: out->J = J_coarse e^p, out->J_in = J - S,
- * out->Gamma = gamma_w[0] J (gamma_w host [1] or NULL for 1) and
+ * out->Gamma = gamma_w[0] J (gamma_w host [1] or NULL for 1), out->Heat =
+ * heat_in[0] J_in + heat_src[0] S (the mesh's weights, art_set_heating) and
  * out->J_exact = J + (J_exact - J) of the coarse sweep (the network predicts
  * J only).  Otherwise out receives art_sweep at nside_fine.  out->exit_sum
  * must be NULL.  *used_fallback (0 or 1) and *est_err (NaN while val_err is
- * unknown) may be NULL.  An err_bound <= 0 always falls back.  Synchronises hip_stream once, to read
- * the out-of-range count. */
+ * unknown) may be NULL.  An err_bound <= 0 always falls back.  Synchronises
+ * hip_stream once, to read the out-of-range count. */
 int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int nside_fine,
                         const float *gamma_w, float err_bound, const art_outputs *out,
                         int *used_fallback, float *est_err, void *hip_stream);

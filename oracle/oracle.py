@@ -6,8 +6,8 @@ with the HIP implementation.
 
 The C library marches the rays and normalises each (direction, cell) average
 literally (Sect. 2.2, eqs rt / path_averaged_intensity / averaged_intensity);
-the last, elementwise step of eq mean_intensity and the rate of eq gamma_diff
-are written out here in numpy float64.
+the last, elementwise step of eq mean_intensity, the rate of eq gamma_diff
+and the heating of eq heat_diff are written out here in numpy float64.
 """
 from __future__ import annotations
 
@@ -135,14 +135,25 @@ def sweep_raw(kappa, S, nside: int, h: float = 1.0, I_bc: float = 0.0,
                 inv_err=float(stats[1]), max_hits=int(stats[2]), nd=nd, d_range=(d0, d1))
 
 
+def heating(J_in, S, heat_in=None, heat_src=None):
+    """Diffuse photo-heating rate with the frequency integrals of eq heat_diff
+    folded into per-bin weights (reading Q12): sum_b heat_in_b J_in_b +
+    heat_src_b S_b over the leading (bin) axis; missing weights are 0."""
+    nb = J_in.shape[0]
+    hi = np.zeros(nb) if heat_in is None else np.asarray(heat_in, dtype=np.float64)
+    hs = np.zeros(nb) if heat_src is None else np.asarray(heat_src, dtype=np.float64)
+    return np.tensordot(hi, J_in, axes=(0, 0)) + np.tensordot(hs, S, axes=(0, 0))
+
+
 def sweep(kappa, S, nside: int, gamma_w=None, h: float = 1.0, I_bc: float = 0.0,
-          nthreads: int = 0):
+          nthreads: int = 0, heat_in=None, heat_src=None):
     """All outputs of one full sweep, float64.
 
     J_in    = (1/N_d) sum_d Ibar^{ave,in}          (eq mean_intensity, J^in)
     J       = J_in + S                              (eq mean_intensity)
     J_exact = J_in + S (1/N_d) sum_d <1 - phi>     (reading Q4)
     Gamma   = sum_b g_b (J_in_b + S_b)              (eq gamma_diff, reading Q5)
+    Heat    = sum_b hin_b J_in_b + hsrc_b S_b       (eq heat_diff, reading Q12)
     """
     raw = sweep_raw(kappa, S, nside, h=h, I_bc=I_bc, nthreads=nthreads)
     S64 = np.asarray(S, dtype=np.float64)
@@ -154,19 +165,20 @@ def sweep(kappa, S, nside: int, gamma_w=None, h: float = 1.0, I_bc: float = 0.0,
     J_exact = J_in + S64 * (raw["ex_sum"] / nd)
     g = np.ones(S64.shape[0]) if gamma_w is None else np.asarray(gamma_w, dtype=np.float64)
     Gamma = np.tensordot(g, J_in + S64, axes=(0, 0))
-    return dict(J_in=J_in, J=J, J_exact=J_exact, Gamma=Gamma, exit_sum=raw["exit_sum"],
+    Heat = heating(J_in, S64, heat_in, heat_src)
+    return dict(J_in=J_in, J=J, J_exact=J_exact, Gamma=Gamma, Heat=Heat, exit_sum=raw["exit_sum"],
                 nseg=raw["nseg"], inv_err=raw["inv_err"], max_hits=raw["max_hits"], nd=nd)
 
 
 def cells(kappa, S, nside: int, cell_idx, gamma_w=None, h: float = 1.0, I_bc: float = 0.0,
-          d_range=None, nthreads: int = 0):
+          d_range=None, nthreads: int = 0, heat_in=None, heat_src=None):
     """The outputs of `sweep` at chosen cells only, float64.
 
     cell_idx: flat x-fastest cell indices.  Each cell's direction sums are
     formed from the rays that cross it, each marched from its entry up to
     the cell (same definitions as the full sweep).  Returns dict with
     jin_sum, ex_sum (nbins, ncells) over d_range, and, for the full
-    direction set, J_in, J, J_exact (nbins, ncells) and Gamma (ncells,).
+    direction set, J_in, J, J_exact (nbins, ncells), Gamma and Heat (ncells,).
     """
     kappa = np.ascontiguousarray(kappa, dtype=np.float64)
     S = np.ascontiguousarray(S, dtype=np.float64)
@@ -193,4 +205,5 @@ def cells(kappa, S, nside: int, cell_idx, gamma_w=None, h: float = 1.0, I_bc: fl
         out["J_exact"] = J_in + S_c * (ex / nd)
         g = np.ones(nb) if gamma_w is None else np.asarray(gamma_w, dtype=np.float64)
         out["Gamma"] = np.tensordot(g, J_in + S_c, axes=(0, 0))
+        out["Heat"] = heating(J_in, S_c, heat_in, heat_src)
     return out

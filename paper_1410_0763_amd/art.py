@@ -22,7 +22,7 @@ MAX_NSIDE = 64
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
-           "art_ndirs", "art_last_error", "art_autotune")
+           "art_ndirs", "art_last_error", "art_autotune", "art_set_heating")
 # include/art_nn.h: layers of the learned surrogate
 NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
@@ -42,9 +42,15 @@ class ArtError(RuntimeError):
         self.code = code
 
 
+OUTPUT_KEYS = ("J_in", "J", "J_exact", "Gamma", "exit_sum", "Heat")
+
+
 class Outputs(ctypes.Structure):
-    _fields_ = [("J_in", ctypes.c_void_p), ("J", ctypes.c_void_p), ("J_exact", ctypes.c_void_p),
-                ("Gamma", ctypes.c_void_p), ("exit_sum", ctypes.c_void_p)]
+    _fields_ = [(k, ctypes.c_void_p) for k in OUTPUT_KEYS]
+
+    @classmethod
+    def of(cls, out: dict):
+        return cls(*(_ptr(out.get(k)) for k in OUTPUT_KEYS))
 
 
 class Tuning(ctypes.Structure):
@@ -82,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.art_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_float)]
     L.art_batch_destroy.argtypes = [vp]
     L.art_ndirs.argtypes = [i]
+    L.art_set_heating.argtypes = [vp, vp, vp]
     L.art_autotune.argtypes = [vp, i, ctypes.POINTER(Tuning), i, ctypes.POINTER(Tuning),
                                ctypes.POINTER(ctypes.c_float), vp]
     L.art_last_error.restype = ctypes.c_char_p
@@ -186,6 +193,16 @@ class Mesh:
         _check(load().art_set_fields(self._h, kappa.shape[0], _ptr(kappa), _ptr(S), on_dev, sp))
         self.nbins = kappa.shape[0]
 
+    def set_heating(self, heat_in=None, heat_src=None):
+        """Weights of the Heat output (art_set_heating): per bin, of J_in and of S."""
+        def arr(v):
+            if v is None:
+                return None
+            a = (ctypes.c_float * self.nbins)(*[float(x) for x in v])
+            return ctypes.cast(a, ctypes.c_void_p), a
+        hi, hs = arr(heat_in), arr(heat_src)
+        _check(load().art_set_heating(self._h, hi[0] if hi else None, hs[0] if hs else None))
+
     # -- tuning ----------------------------------------------------------
     def set_tuning(self, depth, subsets, waves, interleave=2):
         t = Tuning(depth, subsets, waves, interleave)
@@ -236,7 +253,8 @@ class Mesh:
         shp = (nb,) + self.shape
         out = dict(J_in=torch.empty(shp, device=device), J=torch.empty(shp, device=device),
                    J_exact=torch.empty(shp, device=device),
-                   Gamma=torch.empty(self.shape, device=device))
+                   Gamma=torch.empty(self.shape, device=device),
+                   Heat=torch.empty(self.shape, device=device))
         if exit_sum:
             out["exit_sum"] = torch.empty((ndirs(nside), nb), device=device)
         return out
@@ -246,7 +264,7 @@ class Mesh:
         """Full sweep; returns (and fills) a dict of device tensors."""
         if out is None:
             out = self.alloc_outputs(nside, exit_sum)
-        o = Outputs(*(_ptr(out.get(k)) for k in ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
+        o = Outputs.of(out)
         gw = None
         if gamma_w is not None:
             arr = (ctypes.c_float * self.nbins)(*[float(v) for v in gamma_w])
@@ -288,9 +306,7 @@ class Batch:
         n = len(meshes)
         self.meshes = list(meshes)
         self.outs = [m.alloc_outputs(ns) for m, ns in zip(meshes, nsides)]
-        outs = (Outputs * n)(*[Outputs(*(_ptr(o.get(k)) for k in
-                                          ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
-                               for o in self.outs])
+        outs = (Outputs * n)(*[Outputs.of(o) for o in self.outs])
         hs = (ctypes.c_void_p * n)(*[m._h for m in meshes])
         ns_arr = (ctypes.c_int * n)(*[int(v) for v in nsides])
         self._gw_keep = []

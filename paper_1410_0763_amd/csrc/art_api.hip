@@ -68,6 +68,7 @@ struct art_mesh {
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
     art_tuning tune{6, 1, 1, 3};
+    float heat[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // heating weights: J_in terms, then S terms
     int mbd = 0, mbd_key[2] = {-1, -1};   // largest bucket (directions) for (nside, subsets)
 
     float2 *fields = nullptr; size_t fields_cap = 0;
@@ -94,6 +95,11 @@ struct art_mesh {
     ArtMeshDesc desc_host{};
     bool desc_valid = false;
 };
+
+void art_mesh_heating(const art_mesh *m, float hw8[8])
+{
+    for (int i = 0; i < 8; ++i) hw8[i] = m->heat[i];
+}
 
 void art_mesh_fields(const art_mesh *m, int dims[3], int *nb, double *h, const float2 **fields)
 {
@@ -301,6 +307,7 @@ struct art_batch {
     std::vector<int> nside;
     std::vector<art_outputs> outs;
     std::vector<std::array<float, 4>> gw;
+    std::vector<std::array<float, 8>> hw;   // heating weights of each mesh at creation
     float I_bc = 0.0f;
     int waves = 8;
     ArtMeshDesc *descs = nullptr; size_t descs_cap = 0;
@@ -333,8 +340,9 @@ int batch_enqueue(art_batch *B, hipStream_t st)
         art_mesh *m = B->meshes[i];
         const art_outputs &o = B->outs[i];
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields, m->ncell,
-                                    m->nb, 12 * B->nside[i] * B->nside[i], B->gw[i].data(), o.J_in, o.J,
-                                    o.J_exact, o.Gamma, nullptr, nullptr, st));
+                                    m->nb, 12 * B->nside[i] * B->nside[i], B->gw[i].data(),
+                                    B->hw[i].data(), o.J_in, o.J, o.J_exact, o.Gamma, o.Heat,
+                                    nullptr, nullptr, st));
     }
     return ART_OK;
 }
@@ -431,7 +439,10 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
             m->nb = 0;
             return fail(ART_E_INVAL, "kappa must be finite and >= 0 and S finite in every cell");
         }
-        if (m->nb != nbins) m->desc_valid = false;
+        if (m->nb != nbins) {
+            m->desc_valid = false;
+            for (float &w : m->heat) w = 0.0f;   // weights belong to the old bins
+        }
         m->nb = nbins;
         g_err.clear();
         return ART_OK;
@@ -460,8 +471,8 @@ int art_sweep(art_mesh *m, int nside, const float *gamma_w, float I_bc, const ar
         const int nd = 12 * nside * nside;
         if ((rc = run_sweep(m, nside, 0, nd, I_bc, st, out->exit_sum != nullptr))) return rc;
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields,
-                                    m->ncell, m->nb, nd, gw, out->J_in, out->J, out->J_exact,
-                                    out->Gamma, nullptr, nullptr, st));
+                                    m->ncell, m->nb, nd, gw, m->heat, out->J_in, out->J,
+                                    out->J_exact, out->Gamma, out->Heat, nullptr, nullptr, st));
         HIPCHK(hipEventRecord(m->ev[3], st));
         m->timed = true;
         if (out->exit_sum)
@@ -492,7 +503,7 @@ int art_sweep_range(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, 
         const float ones[4] = {1.f, 1.f, 1.f, 1.f};
         HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields,
                                     m->ncell, m->nb, nd, ones, nullptr, nullptr, nullptr, nullptr,
-                                    A1, A2, st));
+                                    nullptr, nullptr, A1, A2, st));
         HIPCHK(hipEventRecord(m->ev[3], st));
         m->timed = true;
         g_err.clear();
@@ -605,6 +616,21 @@ int art_get_tuning(const art_mesh *m, art_tuning *t)
     return ART_OK;
 }
 
+int art_set_heating(art_mesh *m, const float *heat_in, const float *heat_src)
+{
+    if (!m) return fail(ART_E_INVAL, "null mesh");
+    if (m->nb == 0) return fail(ART_E_STATE, "art_set_fields has not been called");
+    float h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < m->nb; ++b) {
+        h[b] = heat_in ? heat_in[b] : 0.0f;
+        h[4 + b] = heat_src ? heat_src[b] : 0.0f;
+        if (!std::isfinite(h[b]) || !std::isfinite(h[4 + b]))
+            return fail(ART_E_INVAL, "heating weights must be finite");
+    }
+    for (int i = 0; i < 8; ++i) m->heat[i] = h[i];
+    return ART_OK;
+}
+
 
 int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const float *const *gamma_w,
                      float I_bc, const art_outputs *outs, int waves, art_batch **out, void *hip_stream)
@@ -638,6 +664,9 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
             if (gamma_w && gamma_w[i])
                 for (int b = 0; b < m->nb; ++b) g[b] = gamma_w[i][b];
             B->gw.push_back(g);
+            std::array<float, 8> h;
+            for (int q = 0; q < 8; ++q) h[q] = m->heat[q];
+            B->hw.push_back(h);
             const int lf = art_march_lds_floats(m->tune.depth, m->nb);
             for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
                 auto key = std::make_tuple((int)w, m->nb, m->tune.interleave);

@@ -53,18 +53,20 @@ __global__ __launch_bounds__(256) void art_fill_kernel(float *__restrict__ p, lo
 }
 
 struct GW {
-    float g[4];
+    float g[4];                 // rate weights of eq gamma_diff
+    float hin[4], hsrc[4];      // heating weights of eq heat_diff (J_in and S terms)
 };
 
 __global__ __launch_bounds__(256) void art_normalize_kernel(
     const float *__restrict__ acc, const int *__restrict__ bucket_start, int nbuckets,
     const float2 *__restrict__ fields, long long ncell, int nb, float inv_nd, GW gw,
     float *__restrict__ J_in, float *__restrict__ J, float *__restrict__ J_exact,
-    float *__restrict__ Gamma, float *__restrict__ A1raw, float *__restrict__ A2raw)
+    float *__restrict__ Gamma, float *__restrict__ Heat, float *__restrict__ A1raw,
+    float *__restrict__ A2raw)
 {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    float gam = 0.0f;
+    float gam = 0.0f, heat = 0.0f;
     for (int b = 0; b < nb; ++b) {
         float a1 = 0.0f, a2 = 0.0f;
         for (int k = 0; k < nbuckets; ++k) {
@@ -82,8 +84,10 @@ __global__ __launch_bounds__(256) void art_normalize_kernel(
         if (J) J[bc] = jin + s;
         if (J_exact) J_exact[bc] = fmaf(s, a2 * inv_nd, jin);
         gam = fmaf(gw.g[b], jin + s, gam);
+        heat = fmaf(gw.hin[b], jin, fmaf(gw.hsrc[b], s, heat));
     }
     if (Gamma) Gamma[c] = gam;
+    if (Heat) Heat[c] = heat;
 }
 
 __global__ __launch_bounds__(256) void art_exit_sum_kernel(const ArtDir *__restrict__ dirs,
@@ -151,15 +155,20 @@ hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream)
 
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
                                 const float2 *fields, long long ncell, int nb, int nd,
-                                const float *gw4, float *J_in, float *J, float *J_exact,
-                                float *Gamma, float *A1raw, float *A2raw, hipStream_t stream)
+                                const float *gw4, const float *hw8, float *J_in, float *J,
+                                float *J_exact, float *Gamma, float *Heat, float *A1raw,
+                                float *A2raw, hipStream_t stream)
 {
     GW gw;
-    for (int b = 0; b < 4; ++b) gw.g[b] = gw4[b];
+    for (int b = 0; b < 4; ++b) {
+        gw.g[b] = gw4[b];
+        gw.hin[b] = hw8 ? hw8[b] : 0.0f;
+        gw.hsrc[b] = hw8 ? hw8[4 + b] : 0.0f;
+    }
     const long long nblk = (ncell + 255) / 256;
     hipLaunchKernelGGL(art_normalize_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, acc,
                        bucket_start, nbuckets, fields, ncell, nb, 1.0f / (float)nd, gw, J_in, J,
-                       J_exact, Gamma, A1raw, A2raw);
+                       J_exact, Gamma, Heat, A1raw, A2raw);
     return hipGetLastError();
 }
 

@@ -71,8 +71,11 @@ hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny,
                              hipStream_t stream);
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
                                 const float2 *fields, long long ncell, int nb, int nd,
-                                const float *gw4, float *J_in, float *J, float *J_exact,
-                                float *Gamma, float *A1raw, float *A2raw, hipStream_t stream);
+                                const float *gw4, const float *hw8, float *J_in, float *J,
+                                float *J_exact, float *Gamma, float *Heat, float *A1raw,
+                                float *A2raw, hipStream_t stream);
+// Heating weights of a mesh (art_set_heating): hin[4] then hsrc[4].
+void art_mesh_heating(const art_mesh *mesh, float hw8[8]);
 hipError_t art_launch_exit_sum(const ArtDir *dirs, int nd, const float *state, int nx, int ny,
                                int nz, int nb, float I_bc, float *exit_sum, hipStream_t stream);
 hipError_t art_launch_fill(float *p, long long n, float v, hipStream_t stream);

@@ -76,16 +76,19 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ J
                                                      const float *__restrict__ Jc,
                                                      const float *__restrict__ Jexc,
                                                      const float2 *__restrict__ rec, int nb,
-                                                     float g0, long long V, float *__restrict__ J,
+                                                     float g0, float h_in, float h_src, long long V,
+                                                     float *__restrict__ J,
                                                      float *__restrict__ J_in,
                                                      float *__restrict__ J_exact,
-                                                     float *__restrict__ Gamma)
+                                                     float *__restrict__ Gamma,
+                                                     float *__restrict__ Heat)
 {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const float j = Js[v];
+    const float j = Js[v], s = rec[v * nb].y;
     if (J) J[v] = j;
-    if (J_in) J_in[v] = j - rec[v * nb].y;
+    if (J_in) J_in[v] = j - s;
+    if (Heat) Heat[v] = fmaf(h_in, j - s, h_src * s);
     if (J_exact) J_exact[v] = j + (Jexc[v] - Jc[v]);
     if (Gamma) Gamma[v] = g0 * j;
 }
@@ -709,9 +712,11 @@ int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int 
     if (est_err) *est_err = est;
     if (used_fallback) *used_fallback = accept ? 0 : 1;
     if (!accept) return art_sweep(mesh, nside_fine, gamma_w, 0.0f, out, hip_stream);
+    float hw[8];
+    art_mesh_heating(mesh, hw);
     hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, s->Js, s->Jc, s->Jexc,
-                       rec, nb, gamma_w ? gamma_w[0] : 1.0f, V, out->J, out->J_in, out->J_exact,
-                       out->Gamma);
+                       rec, nb, gamma_w ? gamma_w[0] : 1.0f, hw[0], hw[4], V, out->J, out->J_in,
+                       out->J_exact, out->Gamma, out->Heat);
     return launch_status("art_sweep_surrogate (outputs)");
 }
 

@@ -19,7 +19,9 @@ Recipes (all seeded with numpy PCG64):
   kappa = kappa0 * n * x_HI, recombination-like source S ~ n^2 (1 - x_HI)
   normalised to mean 1, optional dense spheres multiplying kappa by 100, and
   frequency bins nu_b/nu_0 = 1 + b/4 with kappa_b = kappa (nu_b/nu_0)^-3,
-  S_b = S.
+  S_b = S, rate weights g_b = (nu_b/nu_0)^-4 / nbins and heating weights
+  g_b (1 - nu_0/nu_b + 1/20) (of J_in) and g_b / 20 (of S), synthetic values
+  of the shape of eq heat_diff's per-bin integrals.
 """
 from __future__ import annotations
 
@@ -93,6 +95,8 @@ class Medium:
     I_bc: float = 0.0
     density: np.ndarray | None = None   # (nz, ny, nx) float32, when defined
     x_hi: np.ndarray | None = None      # (nz, ny, nx) float32, when defined
+    heat_in: np.ndarray | None = None   # (nbins,) heating weights of J_in, when defined
+    heat_src: np.ndarray | None = None  # (nbins,) heating weights of S, when defined
 
     @property
     def shape(self):
@@ -130,7 +134,9 @@ def clumpy_medium(shape, nside, sigma_ln, seed, kappa0=0.5, nbins=1,
     gw = (nu ** -4.0) / nbins
     return Medium(name, kappa.astype(np.float32), S.astype(np.float32), nside,
                   gw.astype(np.float32), density=n.astype(np.float32),
-                  x_hi=x_hi.astype(np.float32))
+                  x_hi=x_hi.astype(np.float32),
+                  heat_in=(gw * (1.0 - 1.0 / nu + 0.05)).astype(np.float32),
+                  heat_src=(gw * 0.05).astype(np.float32))
 
 
 # ---- the five workloads -------------------------------------------------

@@ -143,7 +143,7 @@ def sweep_surrogate(mesh, model, nside_coarse=2, nside_fine=16, err_bound=0.05, 
     """art_sweep_surrogate: returns (outputs dict, used_fallback, est_err)."""
     if out is None:
         out = mesh.alloc_outputs(nside_fine)
-    o = Outputs(*(_ptr(out.get(k)) for k in ("J_in", "J", "J_exact", "Gamma")), None)
+    o = Outputs.of({k: v for k, v in out.items() if k != "exit_sum"})
     gw = None
     if gamma_w is not None:
         arr = (ctypes.c_float * 1)(float(gamma_w[0]))

@@ -44,6 +44,8 @@ def gpu_sweep(medium, tuning=None, I_bc=None, exit_sum=True):
         k = torch.from_numpy(medium.kappa).cuda()
         s = torch.from_numpy(medium.S).cuda()
         m.set_fields(k, s)
+        if medium.heat_in is not None:
+            m.set_heating(medium.heat_in, medium.heat_src)
         out = m.sweep(medium.nside, gamma_w=medium.gamma_w,
                       I_bc=medium.I_bc if I_bc is None else I_bc, exit_sum=exit_sum)
         torch.cuda.synchronize()
@@ -52,14 +54,20 @@ def gpu_sweep(medium, tuning=None, I_bc=None, exit_sum=True):
 
 def oracle_sweep(medium, I_bc=None, nthreads=0):
     from oracle import oracle as O
+    h64 = (lambda a: None if a is None else a.astype(np.float64))
     return O.sweep(medium.kappa.astype(np.float64), medium.S.astype(np.float64), medium.nside,
                    gamma_w=medium.gamma_w.astype(np.float64), h=medium.cell_size,
-                   I_bc=medium.I_bc if I_bc is None else I_bc, nthreads=nthreads)
+                   I_bc=medium.I_bc if I_bc is None else I_bc, nthreads=nthreads,
+                   heat_in=h64(medium.heat_in), heat_src=h64(medium.heat_src))
 
 
 def compare_all(medium, gpu, ref, report=None, rtol=RTOL):
     for key in ("J_in", "J", "J_exact", "Gamma"):
         check(f"{medium.name}:{key}", gpu[key], ref[key], rtol=rtol, report=report)
+    if medium.heat_in is not None:
+        check(f"{medium.name}:Heat", gpu["Heat"], ref["Heat"], rtol=rtol, report=report)
+    else:
+        assert not np.any(gpu["Heat"]), "Heat must be 0 without heating weights"
     if "exit_sum" in gpu:
         # per direction and bin, relative to the largest exit sum of that bin
         g = gpu["exit_sum"].astype(np.float64)

@@ -103,7 +103,10 @@ def test_host_only_calls():
     assert L.art_set_tuning(h, ctypes.byref(ok)) == 0
     assert L.art_get_tuning(h, ctypes.byref(t)) == 0
     assert (t.depth, t.subsets, t.waves, t.interleave) == (16, 2, 4, 4)
-    # sweep before set_fields is a state error, caught before any GPU work
+    # heating weights and a sweep before set_fields are state errors, caught
+    # before any GPU work
+    assert L.art_set_heating(h, None, None) == -4
+    assert L.art_set_heating(None, None, None) == -1
     o = art.Outputs()
     assert L.art_sweep(h, 2, None, ctypes.c_float(0.0), ctypes.byref(o), None) == -4
     assert L.art_destroy_mesh(h) == 0

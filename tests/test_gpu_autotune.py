@@ -18,6 +18,7 @@ def test_autotune_parity_and_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     with art.Mesh(nx, ny, nz) as mesh:
         mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        mesh.set_heating(m.heat_in, m.heat_src)
         r1 = mesh.autotune(m.nside, cache_path=cache)
         print(r1, flush=True)
         assert not r1["cached"] and r1["sweep_ms"] > 0

@@ -25,6 +25,8 @@ def test_batch_matches_oracle_and_replays():
         mesh.set_tuning(depth=[8, 16, 5, 32, 3, 12][i % 6], subsets=1 + i % 2, waves=4,
                         interleave=[1, 2, 4][i % 3])
         mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        if m.heat_in is not None:
+            mesh.set_heating(m.heat_in, m.heat_src)
         meshes.append(mesh)
     batch = art.Batch(meshes, [m.nside for m in meds], [m.gamma_w for m in meds], waves=4)
     refs = [oracle_sweep(m) for m in meds]
@@ -35,7 +37,7 @@ def test_batch_matches_oracle_and_replays():
         got = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
         print(f"replay {rep}: {st}", flush=True)
         for m, g, r in zip(meds, got, refs):
-            for key in ("J_in", "J", "J_exact", "Gamma"):
+            for key in ("J_in", "J", "J_exact", "Gamma") + (("Heat",) if m.heat_in is not None else ()):
                 check(f"batch:{m.name}:{key}", g[key], r[key])
         if first is None:
             first = got

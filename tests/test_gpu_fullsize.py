@@ -44,6 +44,7 @@ def test_plain_256_sampled_cells():
     with art.Mesh(nx, ny, nz, m.cell_size) as mesh:
         print(f"tuning {mesh.get_tuning()}", flush=True)
         mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        mesh.set_heating(m.heat_in, m.heat_src)
         out = mesh.sweep(m.nside, gamma_w=m.gamma_w, I_bc=m.I_bc, exit_sum=False)
         torch.cuda.synchronize()
         g = {k: v.cpu().numpy() for k, v in out.items()}
@@ -52,7 +53,8 @@ def test_plain_256_sampled_cells():
     assert np.all(g["J_in"] >= 0.0)
     idx = _sample_cells((nz, ny, nx), np.random.default_rng(2024), m.kappa[0])
     ref = O.cells(m.kappa, m.S, m.nside, idx, gamma_w=m.gamma_w, h=m.cell_size, I_bc=m.I_bc,
-                  nthreads=min(16, os.cpu_count() or 1))
+                  nthreads=min(16, os.cpu_count() or 1), heat_in=m.heat_in, heat_src=m.heat_src)
     for key in ("J_in", "J", "J_exact"):
         check(f"plain_256 sampled:{key}", g[key].reshape(nb, -1)[:, idx], ref[key])
     check("plain_256 sampled:Gamma", g["Gamma"].ravel()[idx], ref["Gamma"])
+    check("plain_256 sampled:Heat", g["Heat"].ravel()[idx], ref["Heat"])

@@ -313,7 +313,7 @@ def test_gate_and_argument_errors():
     out, fb, est = SG.sweep_surrogate(mesh, model, 1, 2, err_bound=1e9)
     assert not fb and est == 0.0
     o = mesh.alloc_outputs(2, exit_sum=True)
-    outs = art.Outputs(*(art._ptr(o.get(q)) for q in ("J_in", "J", "J_exact", "Gamma", "exit_sum")))
+    outs = art.Outputs.of(o)
     rc = art.load().art_sweep_surrogate(mesh._h, model._h, 1, 2, None, 1e9, outs, None, None,
                                         art._stream_ptr(None))
     assert rc == -1 and b"exit" in art.load().art_last_error()
@@ -435,6 +435,7 @@ def test_surrogate_gain_and_fallback():
     # the accepted outputs against the same steps through the other entry points
     p = test[0]
     mesh.set_fields(p["k"], p["s"])
+    mesh.set_heating([0.3], [0.1])
     out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0, gamma_w=[0.5])
     assert not fb
     c = mesh.sweep(2)
@@ -446,6 +447,9 @@ def test_surrogate_gain_and_fallback():
     assert torch.allclose(Js, Jm, rtol=2e-6, atol=0)
     assert torch.allclose(out["J_in"].reshape(-1), Js - p["s"].reshape(-1), rtol=0, atol=1e-6 * Js.max().item())
     assert torch.allclose(out["Gamma"].reshape(-1), 0.5 * Js, rtol=1e-6, atol=0)
+    Jin = Js - p["s"].reshape(-1)
+    assert torch.allclose(out["Heat"].reshape(-1), 0.3 * Jin + 0.1 * p["s"].reshape(-1), rtol=1e-5,
+                          atol=1e-6 * Js.max().item())
     assert torch.allclose(out["J_exact"].reshape(-1), Js + (c["J_exact"] - c["J"]).reshape(-1),
                           rtol=0, atol=1e-6 * Js.max().item())
     # time: coarse sweep + inference against the fine sweep
