@@ -60,10 +60,20 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsi
 // (the lane holds column lane % 32).
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// One wave: 4 output rows (y0 .. y0+3 at one z) x 32 voxels along x x 32
-// output channels.  For each (dz, dx) and group of 16 input channels the 6
-// input rows y0-1 .. y0+4 and the 3 weight fragments (dy = -1, 0, 1) are
-// loaded once and feed 12 MFMAs.
+// One workgroup of 4 waves: output rows y0 .. y0+15 (4 per wave) x 32 voxels
+// along x at one z, 32 output channels.  For each dz the input plane z + dz
+// (rows y0-1 .. y0+16, voxels x0-1 .. x0+32, all input channels; zero outside
+// the mesh) and the nine weight taps of that dz are staged in LDS once; each
+// wave then takes its 6 input rows and the 3 weight fragments of every
+// (dx, 16-channel group) from LDS and issues 12 MFMAs per (dx, group, ...)
+// set.  Rows of LDS data are padded by 16 bytes against bank conflicts.
+constexpr int CONV_ROWS = 18, CONV_COLS = 34;
+template <int CIN> constexpr int conv_vs() { return CIN + 8; }        // bf16 per staged voxel
+template <int CIN> constexpr int conv_lds_bytes()
+{
+    return (CONV_ROWS * CONV_COLS + 9 * 32) * conv_vs<CIN>() * 2;
+}
+
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
                                                        const uint16_t *__restrict__ w,
@@ -72,16 +82,15 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
                                                        uint16_t *__restrict__ y,
                                                        float *__restrict__ y0)
 {
-    constexpr int R = 4;
-    __shared__ float tile[4][32][33];
+    constexpr int R = 4, VS = conv_vs<CIN>(), NQ = CIN / 8;   // 16-byte chunks per voxel
+    extern __shared__ __align__(16) uint16_t smem[];
+    uint16_t *sx = smem;                                       // [18][34][VS]
+    uint16_t *sw = smem + CONV_ROWS * CONV_COLS * VS;          // [9][32][VS]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ntw = W / 32, nty = (H + R - 1) / R;
-    const long long ntiles = (long long)D * nty * ntw;
-    const long long tid = (long long)blockIdx.x * 4 + wave;
-    const bool active = tid < ntiles;
-    const long long t = active ? tid : 0;
+    const int ntw = W / 32, nty = (H + 4 * R - 1) / (4 * R);
+    const long long t = blockIdx.x;
     const int xt = (int)(t % ntw), ty = (int)((t / ntw) % nty), zz0 = (int)(t / ((long long)ntw * nty));
-    const int yb = ty * R;
+    const int yb = ty * 4 * R, x0 = xt * 32;
     const int m = lane & 31, kh = lane >> 5;
     const long long V = (long long)D * H * W;
     const rsrc_t rX = nn_rsrc(x, V * CIN * 2);
@@ -91,24 +100,35 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
     for (int q = 0; q < R; ++q) acc[q] = f32x16{};
     for (int dz = -1; dz <= 1; ++dz) {
         const int zz = zz0 + dz;
+        if (zz < 0 || zz >= D) continue;                       // uniform over the workgroup
+        __syncthreads();                                       // the previous plane is consumed
+        for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * NQ; c += 256) {
+            const int q = c % NQ, vox = c / NQ, col = vox % CONV_COLS, row = vox / CONV_COLS;
+            const int yy = yb - 1 + row, xx = x0 - 1 + col;
+            const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const unsigned off = ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + q * 16) : NN_OOB;
+            *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
+        }
+        for (int c = threadIdx.x; c < 9 * 32 * NQ; c += 256) {
+            const int q = c % NQ, row = c / NQ;                 // row = tap in dz * 32 + co
+            const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + q * 16);
+            *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
-            const int xx = xt * 32 + m + dx;
-            const bool okzx = zz >= 0 && zz < D && xx >= 0 && xx < W;
 #pragma unroll
             for (int ks = 0; ks < CIN / 16; ++ks) {
                 bf16x8 a[R + 2];
 #pragma unroll
-                for (int r = 0; r < R + 2; ++r) {
-                    const int yy = yb - 1 + r;
-                    const bool ok = okzx && yy >= 0 && yy < H;
-                    const unsigned off =
-                        ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2) : NN_OOB;
-                    a[r] = load8(rX, off + (16 * ks + 8 * kh) * 2);
-                }
+                for (int r = 0; r < R + 2; ++r)
+                    a[r] = *reinterpret_cast<const bf16x8 *>(
+                        sx + ((wave * R + r) * CONV_COLS + m + 1 + dx) * VS + 16 * ks + 8 * kh);
 #pragma unroll
                 for (int dy = -1; dy <= 1; ++dy) {
-                    const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-                    const bf16x8 bw = load8(rW, (unsigned)(((tap * 32 + m) * CIN + 16 * ks + 8 * kh) * 2));
+                    const int tl = (dy + 1) * 3 + (dx + 1);
+                    const bf16x8 bw =
+                        *reinterpret_cast<const bf16x8 *>(sw + (tl * 32 + m) * VS + 16 * ks + 8 * kh);
 #pragma unroll
                     for (int q = 0; q < R; ++q)
                         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q + dy + 1], bw, acc[q], 0, 0, 0);
@@ -116,18 +136,20 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
             }
         }
     }
+    __syncthreads();                                           // LDS now holds the output tiles
+    float (*tile)[32][33] = reinterpret_cast<float (*)[32][33]>(smem) + wave;
     const float bm = bias ? bias[m] : 0.0f;
     for (int q = 0; q < R; ++q) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             float v = acc[q][r] + bm;
             if (relu) v = fmaxf(v, 0.0f);
-            tile[wave][acc_row(r, lane)][m] = v;
+            (*tile)[acc_row(r, lane)][m] = v;
         }
         __syncthreads();
-        const int yq = yb + q;
-        if (active && yq < H) {
-            const long long v0 = ((long long)zz0 * H + yq) * W + xt * 32;
+        const int yq = yb + wave * R + q;
+        if (yq < H) {
+            const long long v0 = ((long long)zz0 * H + yq) * W + x0;
             if (y) {
                 const int row = lane >> 1, c0 = (lane & 1) * 16;
                 u32x4 p[2];
@@ -136,14 +158,13 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int c = c0 + 8 * h + 2 * e;
-                        p[h][e] = (unsigned)f2bf(tile[wave][row][c]) |
-                                  ((unsigned)f2bf(tile[wave][row][c + 1]) << 16);
+                        p[h][e] = (unsigned)f2bf((*tile)[row][c]) | ((unsigned)f2bf((*tile)[row][c + 1]) << 16);
                     }
                 u32x4 *dst = reinterpret_cast<u32x4 *>(y + (v0 + row) * 32 + c0);
                 dst[0] = p[0];
                 dst[1] = p[1];
             }
-            if (y0 && lane < 32) y0[v0 + lane] = tile[wave][lane][0];
+            if (y0 && lane < 32) y0[v0 + lane] = (*tile)[lane][0];
         }
         __syncthreads();
     }
@@ -461,15 +482,26 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
     if ((long long)D * H * W * 64 >= (1ll << 31))
         return art_set_error(ART_E_UNSUPPORTED, "art_conv3d_fwd: activation tensor above 2 GiB");
     hipStream_t st = (hipStream_t)hip_stream;
-    const long long tiles = (long long)D * ((H + 3) / 4) * (W / 32);
+    const long long tiles = (long long)D * ((H + 15) / 16) * (W / 32);
     const auto *xp = (const uint16_t *)x;
     const auto *wp = (const uint16_t *)w_k;
+    static bool configured = false;   // LDS above the 64 KiB default needs an opt-in
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)conv_fwd_kernel<16>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<16>());
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)conv_fwd_kernel<32>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<32>());
+        if (e != hipSuccess)
+            return art_set_error(ART_E_HIP, (std::string("art_conv3d_fwd: ") + hipGetErrorString(e)).c_str());
+        configured = true;
+    }
     if (cin == 16)
-        hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3(blocks_for(tiles, 4)), dim3(256), 0, st, xp, wp,
-                           bias, D, H, W, relu, (uint16_t *)y, y0);
+        hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3((unsigned)tiles), dim3(256), conv_lds_bytes<16>(), st,
+                           xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
     else
-        hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3(blocks_for(tiles, 4)), dim3(256), 0, st, xp, wp,
-                           bias, D, H, W, relu, (uint16_t *)y, y0);
+        hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3((unsigned)tiles), dim3(256), conv_lds_bytes<32>(), st,
+                           xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
     return launch_status("art_conv3d_fwd");
 }
 
