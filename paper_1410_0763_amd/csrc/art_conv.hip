@@ -60,13 +60,14 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsi
 // (the lane holds column lane % 32).
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// One workgroup of 4 waves: output rows y0 .. y0+15 (4 per wave) x 32 voxels
+// One workgroup of 8 waves: output rows y0 .. y0+15 (2 per wave) x 32 voxels
 // along x at one z, 32 output channels.  For each dz the input plane z + dz
 // (rows y0-1 .. y0+16, voxels x0-1 .. x0+32, all input channels; zero outside
 // the mesh) and the nine weight taps of that dz are staged in LDS once; each
-// wave then takes its 6 input rows and the 3 weight fragments of every
-// (dx, 16-channel group) from LDS and issues 12 MFMAs per (dx, group, ...)
-// set.  Rows of LDS data are padded by 16 bytes against bank conflicts.
+// wave then takes its 4 input rows and the 3 weight fragments of every
+// (dx, 16-channel group) from LDS for 6 MFMAs.  Rows of LDS data are padded
+// by 16 bytes against bank conflicts.  Two workgroups fit a CU's LDS, i.e.
+// 4 waves per SIMD.
 constexpr int CONV_ROWS = 18, CONV_COLS = 34;
 template <int CIN> constexpr int conv_vs() { return CIN + 8; }        // bf16 per staged voxel
 template <int CIN> constexpr int conv_lds_bytes()
@@ -75,22 +76,22 @@ template <int CIN> constexpr int conv_lds_bytes()
 }
 
 template <int CIN>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restrict__ x,
+__global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restrict__ x,
                                                        const uint16_t *__restrict__ w,
                                                        const float *__restrict__ bias, int D,
                                                        int H, int W, int relu,
                                                        uint16_t *__restrict__ y,
                                                        float *__restrict__ y0)
 {
-    constexpr int R = 4, VS = conv_vs<CIN>(), NQ = CIN / 8;   // 16-byte chunks per voxel
+    constexpr int R = 2, VS = conv_vs<CIN>(), NQ = CIN / 8;   // 16-byte chunks per voxel
     extern __shared__ __align__(16) uint16_t smem[];
     uint16_t *sx = smem;                                       // [18][34][VS]
     uint16_t *sw = smem + CONV_ROWS * CONV_COLS * VS;          // [9][32][VS]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ntw = W / 32, nty = (H + 4 * R - 1) / (4 * R);
+    const int ntw = W / 32, nty = (H + 2 * 8 - 1) / 16;
     const long long t = blockIdx.x;
     const int xt = (int)(t % ntw), ty = (int)((t / ntw) % nty), zz0 = (int)(t / ((long long)ntw * nty));
-    const int yb = ty * 4 * R, x0 = xt * 32;
+    const int yb = ty * 16, x0 = xt * 32;
     const int m = lane & 31, kh = lane >> 5;
     const long long V = (long long)D * H * W;
     const rsrc_t rX = nn_rsrc(x, V * CIN * 2);
@@ -102,14 +103,14 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const uint16_t *__restric
         const int zz = zz0 + dz;
         if (zz < 0 || zz >= D) continue;                       // uniform over the workgroup
         __syncthreads();                                       // the previous plane is consumed
-        for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * NQ; c += 256) {
+        for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * NQ; c += 512) {
             const int q = c % NQ, vox = c / NQ, col = vox % CONV_COLS, row = vox / CONV_COLS;
             const int yy = yb - 1 + row, xx = x0 - 1 + col;
             const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
             const unsigned off = ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + q * 16) : NN_OOB;
             *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
         }
-        for (int c = threadIdx.x; c < 9 * 32 * NQ; c += 256) {
+        for (int c = threadIdx.x; c < 9 * 32 * NQ; c += 512) {
             const int q = c % NQ, row = c / NQ;                 // row = tap in dz * 32 + co
             const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + q * 16);
             *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
@@ -497,10 +498,10 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
         configured = true;
     }
     if (cin == 16)
-        hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3((unsigned)tiles), dim3(256), conv_lds_bytes<16>(), st,
+        hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3((unsigned)tiles), dim3(512), conv_lds_bytes<16>(), st,
                            xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
     else
-        hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3((unsigned)tiles), dim3(256), conv_lds_bytes<32>(), st,
+        hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3((unsigned)tiles), dim3(512), conv_lds_bytes<32>(), st,
                            xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
     return launch_status("art_conv3d_fwd");
 }
