@@ -61,19 +61,16 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((unsi
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
 // One workgroup of 8 waves: output rows y0 .. y0+15 (2 per wave) x 32 voxels
-// along x at one z, 32 output channels.  For each dz the input plane z + dz
-// (rows y0-1 .. y0+16, voxels x0-1 .. x0+32, all input channels; zero outside
-// the mesh) and the nine weight taps of that dz are staged in LDS once; each
-// wave then takes its 4 input rows and the 3 weight fragments of every
-// (dx, 16-channel group) from LDS for 6 MFMAs.  Rows of LDS data are padded
-// by 16 bytes against bank conflicts.  Two workgroups fit a CU's LDS, i.e.
-// 4 waves per SIMD.
+// along x at one z, 32 output channels.  For each dz and group of 16 input
+// channels, that group of the input plane z + dz (rows y0-1 .. y0+16, voxels
+// x0-1 .. x0+32; zero outside the mesh) and of the nine weight taps of that
+// dz are staged in LDS once; each wave then takes its 4 input rows and the
+// 3 weight fragments of every dx from LDS for 6 MFMAs.  Staged voxels are
+// padded to 48 bytes against bank conflicts; 43 KB per workgroup lets three
+// workgroups share a CU (6 waves per SIMD).
 constexpr int CONV_ROWS = 18, CONV_COLS = 34;
-template <int CIN> constexpr int conv_vs() { return CIN + 8; }        // bf16 per staged voxel
-template <int CIN> constexpr int conv_lds_bytes()
-{
-    return (CONV_ROWS * CONV_COLS + 9 * 32) * conv_vs<CIN>() * 2;
-}
+constexpr int CONV_VS = 24;                                          // bf16 per staged voxel (16 + pad)
+template <int CIN> constexpr int conv_lds_bytes() { return (CONV_ROWS * CONV_COLS + 9 * 32) * CONV_VS * 2; }
 
 template <int CIN>
 __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restrict__ x,
@@ -83,12 +80,12 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
                                                        uint16_t *__restrict__ y,
                                                        float *__restrict__ y0)
 {
-    constexpr int R = 2, VS = conv_vs<CIN>(), NQ = CIN / 8;   // 16-byte chunks per voxel
+    constexpr int R = 2, VS = CONV_VS;
     extern __shared__ __align__(16) uint16_t smem[];
     uint16_t *sx = smem;                                       // [18][34][VS]
     uint16_t *sw = smem + CONV_ROWS * CONV_COLS * VS;          // [9][32][VS]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ntw = W / 32, nty = (H + 2 * 8 - 1) / 16;
+    const int ntw = W / 32, nty = (H + 15) / 16;
     const long long t = blockIdx.x;
     const int xt = (int)(t % ntw), ty = (int)((t / ntw) % nty), zz0 = (int)(t / ((long long)ntw * nty));
     const int yb = ty * 16, x0 = xt * 32;
@@ -102,34 +99,32 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
     for (int dz = -1; dz <= 1; ++dz) {
         const int zz = zz0 + dz;
         if (zz < 0 || zz >= D) continue;                       // uniform over the workgroup
-        __syncthreads();                                       // the previous plane is consumed
-        for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * NQ; c += 512) {
-            const int q = c % NQ, vox = c / NQ, col = vox % CONV_COLS, row = vox / CONV_COLS;
-            const int yy = yb - 1 + row, xx = x0 - 1 + col;
-            const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-            const unsigned off = ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + q * 16) : NN_OOB;
-            *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
-        }
-        for (int c = threadIdx.x; c < 9 * 32 * NQ; c += 512) {
-            const int q = c % NQ, row = c / NQ;                 // row = tap in dz * 32 + co
-            const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + q * 16);
-            *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
-        }
-        __syncthreads();
+        for (int ks = 0; ks < CIN / 16; ++ks) {
+            __syncthreads();                                   // the previous stage is consumed
+            for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * 2; c += 512) {
+                const int q = c & 1, vox = c >> 1, col = vox % CONV_COLS, row = vox / CONV_COLS;
+                const int yy = yb - 1 + row, xx = x0 - 1 + col;
+                const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+                const unsigned off =
+                    ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + 32 * ks + 16 * q) : NN_OOB;
+                *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
+            }
+            for (int c = threadIdx.x; c < 9 * 32 * 2; c += 512) {
+                const int q = c & 1, row = c >> 1;               // row = tap in dz * 32 + co
+                const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + 32 * ks + 16 * q);
+                *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
+            }
+            __syncthreads();
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-#pragma unroll
-            for (int ks = 0; ks < CIN / 16; ++ks) {
+            for (int dx = -1; dx <= 1; ++dx) {
                 bf16x8 a[R + 2];
 #pragma unroll
                 for (int r = 0; r < R + 2; ++r)
-                    a[r] = *reinterpret_cast<const bf16x8 *>(
-                        sx + ((wave * R + r) * CONV_COLS + m + 1 + dx) * VS + 16 * ks + 8 * kh);
+                    a[r] = *reinterpret_cast<const bf16x8 *>(sx + ((wave * R + r) * CONV_COLS + m + 1 + dx) * VS + 8 * kh);
 #pragma unroll
                 for (int dy = -1; dy <= 1; ++dy) {
                     const int tl = (dy + 1) * 3 + (dx + 1);
-                    const bf16x8 bw =
-                        *reinterpret_cast<const bf16x8 *>(sw + (tl * 32 + m) * VS + 16 * ks + 8 * kh);
+                    const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(sw + (tl * 32 + m) * VS + 8 * kh);
 #pragma unroll
                     for (int q = 0; q < R; ++q)
                         acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q + dy + 1], bw, acc[q], 0, 0, 0);
