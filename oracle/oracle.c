@@ -525,3 +525,172 @@ int oracle_cells(int nx, int ny, int nz, double h, int nbins,
     free(n);
     return failed ? -2 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Point sources (Sect. 2.3, RT from point radiation sources, and the       */
+/* photon-conserving rates of Appendix A).                                  */
+/*                                                                          */
+/* Source at p (cell units, inside the closed box), target cell c with     */
+/* centre q.  The light ray is the line from p through q, unit direction   */
+/* u = (q - p) / |q - p| (reading P2: u = +x when p == q).  r_in and r_out  */
+/* are the distances from p where the line enters and leaves cell c        */
+/* (r_in = 0 when p lies in c).  tau_b sums kappa_b h dl over the cells the */
+/* line crosses before c; dtau_b = kappa_b(c) h (r_out - r_in) is the       */
+/* radial optical depth of the imaginary shell r_in..r_out.  The photons    */
+/* the shell absorbs per unit time are Q_b e^{-tau_b} (1 - e^{-dtau_b})     */
+/* (Q_b: photon rate of the source in bin b); divided by the absorbers in   */
+/* the shell, n_c (4 pi / 3)(r_out^3 - r_in^3) h^3, they give the rate per  */
+/* absorber (eq pc_gamma with one absorbing species, so that the species'   */
+/* share of dtau is 1), and weighted by e_b (the energy per absorbed photon */
+/* above threshold) the heating rate per absorber.  Sums over sources and   */
+/* bins.  Cells with n_c <= 0 get 0.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Segments of the line from p towards cell c, up to where it enters c:
+   every integer-plane crossing in (0, r_in) sorted; a gap longer than a
+   sliver belongs to the cell holding its midpoint.  Writes the cells and
+   lengths (cell units) of the segments before c, r_in and r_out; returns the
+   number of segments. */
+static int point_path(const int *N, const double *p, const int *c, double *buf, int *cell,
+                      double *len, double *r_in, double *r_out)
+{
+    double q[3], u[3], dist = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        q[ax] = c[ax] + 0.5;
+        u[ax] = q[ax] - p[ax];
+        dist += u[ax] * u[ax];
+    }
+    dist = sqrt(dist);
+    if (dist > 0.0) {
+        for (int ax = 0; ax < 3; ++ax) u[ax] /= dist;
+    } else {
+        u[0] = 1.0; u[1] = 0.0; u[2] = 0.0;
+    }
+    /* slab intersection of the line with the cell's box */
+    double tin = -INFINITY, tout = INFINITY;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (u[ax] == 0.0) continue;       /* then p[ax] = q[ax] lies inside the slab */
+        const double t0 = (c[ax] - p[ax]) / u[ax], t1 = (c[ax] + 1.0 - p[ax]) / u[ax];
+        tin = fmax(tin, fmin(t0, t1));
+        tout = fmin(tout, fmax(t0, t1));
+    }
+    if (tin < 0.0) tin = 0.0;
+    *r_in = tin;
+    *r_out = tout;
+    int nb = 0;
+    buf[nb++] = 0.0;
+    buf[nb++] = tin;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (u[ax] == 0.0) continue;
+        const double x1 = p[ax] + u[ax] * tin;
+        const double lo = fmin(p[ax], x1), hi = fmax(p[ax], x1);
+        for (double m = floor(lo) + 1.0; m < hi; m += 1.0) {
+            const double t = (m - p[ax]) / u[ax];
+            if (t > 0.0 && t < tin) buf[nb++] = t;
+        }
+    }
+    qsort(buf, nb, sizeof(double), cmp_double);
+    int ns = 0;
+    for (int k = 0; k + 1 < nb; ++k) {
+        const double ta = buf[k], tb = buf[k + 1];
+        if (!(tb - ta > ORACLE_SLIVER)) continue;
+        int ci[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            int v = (int)floor(p[ax] + u[ax] * 0.5 * (ta + tb));
+            if (v < 0) v = 0;
+            if (v > N[ax] - 1) v = N[ax] - 1;
+            ci[ax] = v;
+        }
+        if (ci[0] == c[0] && ci[1] == c[1] && ci[2] == c[2]) continue;   /* rounding at r_in */
+        cell[ns] = (ci[2] * N[1] + ci[1]) * N[0] + ci[0];
+        len[ns] = tb - ta;
+        ++ns;
+    }
+    return ns;
+}
+
+/* One (source, cell) pair: tau[b], dtau[b] (optical depths, h included),
+   r_in, r_out (cell units).  Returns 0, or -1 for a bad argument. */
+int oracle_point_pair(int nx, int ny, int nz, double h, int nbins, const double *kappa,
+                      const double *p, int64_t cid, double *tau, double *dtau,
+                      double *r_in, double *r_out)
+{
+    const int N[3] = {nx, ny, nz};
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    if (nx < 1 || ny < 1 || nz < 1 || nbins < 1 || !(h > 0.0) || cid < 0 || cid >= ncell) return -1;
+    for (int ax = 0; ax < 3; ++ax)
+        if (!(p[ax] >= 0.0 && p[ax] <= N[ax])) return -1;
+    const int c[3] = {(int)(cid % nx), (int)((cid / nx) % ny), (int)(cid / ((int64_t)nx * ny))};
+    const int mc = max_crossings(N);
+    double *buf = (double *)malloc(sizeof(double) * mc);
+    double *len = (double *)malloc(sizeof(double) * mc);
+    int *cell = (int *)malloc(sizeof(int) * mc);
+    if (!buf || !len || !cell) { free(buf); free(len); free(cell); return -2; }
+    const int ns = point_path(N, p, c, buf, cell, len, r_in, r_out);
+    for (int b = 0; b < nbins; ++b) {
+        double t = 0.0;
+        for (int k = 0; k < ns; ++k) t += kappa[(int64_t)b * ncell + cell[k]] * h * len[k];
+        tau[b] = t;
+        dtau[b] = kappa[(int64_t)b * ncell + cid] * h * (*r_out - *r_in);
+    }
+    free(buf); free(len); free(cell);
+    return 0;
+}
+
+/* Rates at cells[i] (all cells if cells is NULL, ncells = nx ny nz) from
+   nsrc sources: pos [nsrc][3], Q [nsrc][nbins], e [nbins] (NULL: Heat not
+   written); Gamma, Heat [ncells].  Returns 0, -1 (bad argument), -2. */
+int oracle_point(int nx, int ny, int nz, double h, int nbins, const double *kappa,
+                 const double *n_abs, int nsrc, const double *pos, const double *Q,
+                 const double *e, const int64_t *cells, int ncells, double *Gamma,
+                 double *Heat, int nthreads)
+{
+    const int N[3] = {nx, ny, nz};
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    if (nx < 1 || ny < 1 || nz < 1 || nbins < 1 || !(h > 0.0) || nsrc < 0 || ncells < 0) return -1;
+    if (!cells && ncells != ncell) return -1;
+    for (int i = 0; cells && i < ncells; ++i)
+        if (cells[i] < 0 || cells[i] >= ncell) return -1;
+    for (int s = 0; s < nsrc; ++s)
+        for (int ax = 0; ax < 3; ++ax)
+            if (!(pos[3 * s + ax] >= 0.0 && pos[3 * s + ax] <= N[ax])) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    const int mc = max_crossings(N);
+    const double four_pi_3 = 4.0 * M_PI / 3.0;
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : failed)
+    for (int i = 0; i < ncells; ++i) {
+        const int64_t cid = cells ? cells[i] : i;
+        const int c[3] = {(int)(cid % nx), (int)((cid / nx) % ny), (int)(cid / ((int64_t)nx * ny))};
+        double *buf = (double *)malloc(sizeof(double) * mc);
+        double *len = (double *)malloc(sizeof(double) * mc);
+        int *cell = (int *)malloc(sizeof(int) * mc);
+        double g = 0.0, ht = 0.0;
+        if (!buf || !len || !cell) {
+            failed = 1;
+        } else if (n_abs[cid] > 0.0) {
+            for (int s = 0; s < nsrc; ++s) {
+                double rin, rout;
+                const int ns = point_path(N, pos + 3 * s, c, buf, cell, len, &rin, &rout);
+                /* r_out^3 - r_in^3 in factored form (no cancellation) */
+                const double vol = four_pi_3 * h * h * h * (rout - rin) *
+                                   (rout * rout + rout * rin + rin * rin);
+                const double absorbers = n_abs[cid] * vol;
+                for (int b = 0; b < nbins; ++b) {
+                    double tau = 0.0;
+                    for (int k = 0; k < ns; ++k) tau += kappa[(int64_t)b * ncell + cell[k]] * h * len[k];
+                    const double dtau = kappa[(int64_t)b * ncell + cid] * h * (rout - rin);
+                    const double nabs_dot = Q[(int64_t)s * nbins + b] * exp(-tau) * -expm1(-dtau);
+                    g += nabs_dot / absorbers;
+                    if (e) ht += nabs_dot * e[b] / absorbers;
+                }
+            }
+        }
+        Gamma[i] = g;
+        if (Heat) Heat[i] = e ? ht : 0.0;
+        free(buf); free(len); free(cell);
+    }
+    return failed ? -2 : 0;
+}

@@ -7,7 +7,9 @@ with the HIP implementation.
 The C library marches the rays and normalises each (direction, cell) average
 literally (Sect. 2.2, eqs rt / path_averaged_intensity / averaged_intensity);
 the last, elementwise step of eq mean_intensity, the rate of eq gamma_diff
-and the heating of eq heat_diff are written out here in numpy float64.
+and the heating of eq heat_diff are written out here in numpy float64.  It
+also evaluates the photon-conserving rates of point sources (Sect. 2.3 and
+Appendix A), `point` and `point_pair`.
 """
 from __future__ import annotations
 
@@ -53,6 +55,12 @@ def lib():
         L.oracle_cells.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp] +
                                    [ctypes.c_int] * 3 + [ctypes.c_double,
                                                          ctypes.POINTER(ctypes.c_int64),
+                                                         ctypes.c_int, dp, dp, ctypes.c_int])
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.oracle_point_pair.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp,
+                                                              ctypes.c_int64, dp, dp, dp, dp])
+        L.oracle_point.argtypes = ([ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_int, dp, dp,
+                                                         ctypes.c_int, dp, dp, dp, i64p,
                                                          ctypes.c_int, dp, dp, ctypes.c_int])
         _lib = L
     return _lib
@@ -207,3 +215,57 @@ def cells(kappa, S, nside: int, cell_idx, gamma_w=None, h: float = 1.0, I_bc: fl
         out["Gamma"] = np.tensordot(g, J_in + S_c, axes=(0, 0))
         out["Heat"] = heating(J_in, S_c, heat_in, heat_src)
     return out
+
+
+def _kappa4(kappa):
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    return kappa[None] if kappa.ndim == 3 else kappa
+
+
+def point_pair(kappa, p, cell: int, h: float = 1.0):
+    """Optical depths of one (source, cell) pair: dict tau, dtau (nbins,) and
+    r_in, r_out (cell units) of the line from p through the cell's centre."""
+    kappa = _kappa4(kappa)
+    nb, nz, ny, nx = kappa.shape
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    tau = np.zeros(nb)
+    dtau = np.zeros(nb)
+    rin = ctypes.c_double()
+    rout = ctypes.c_double()
+    rc = lib().oracle_point_pair(nx, ny, nz, float(h), nb, _dp(kappa), _dp(pp), int(cell),
+                                 _dp(tau), _dp(dtau), ctypes.byref(rin), ctypes.byref(rout))
+    if rc != 0:
+        raise ValueError(f"oracle_point_pair failed ({rc})")
+    return dict(tau=tau, dtau=dtau, r_in=rin.value, r_out=rout.value)
+
+
+def point(kappa, n_abs, pos, Q, e=None, h: float = 1.0, cell_idx=None, nthreads: int = 0):
+    """Photon-conserving rates per absorber from point sources (Sect. 2.3,
+    Appendix A), float64.
+
+    kappa (nbins, nz, ny, nx) or (nz, ny, nx) per unit length; n_abs (nz, ny,
+    nx) absorber density; pos (nsrc, 3) source positions (x, y, z) in cell
+    units; Q (nsrc, nbins) photon rates; e (nbins,) energy per absorbed photon
+    above threshold or None.  Returns dict Gamma, Heat at cell_idx (flat,
+    x-fastest) or, if None, over the whole mesh (flat)."""
+    kappa = _kappa4(kappa)
+    nb, nz, ny, nx = kappa.shape
+    n = np.ascontiguousarray(n_abs, dtype=np.float64).reshape(-1)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    Q = np.ascontiguousarray(Q, dtype=np.float64).reshape(pos.shape[0], nb)
+    ev = None if e is None else np.ascontiguousarray(e, dtype=np.float64).reshape(nb)
+    if cell_idx is None:
+        idx = None
+        m = nx * ny * nz
+    else:
+        idx = np.ascontiguousarray(cell_idx, dtype=np.int64).ravel()
+        m = idx.size
+    G = np.zeros(m)
+    H = np.zeros(m)
+    rc = lib().oracle_point(nx, ny, nz, float(h), nb, _dp(kappa), _dp(n), pos.shape[0], _dp(pos),
+                            _dp(Q), _dp(ev),
+                            None if idx is None else idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            m, _dp(G), _dp(H), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_point failed ({rc})")
+    return dict(Gamma=G, Heat=H)
