@@ -292,6 +292,49 @@ def bench_surrogate(train_fields=16, steps=800):
     print(json.dumps(rec), flush=True)
 
 
+def bench_point(steps=5, cpu=True):
+    """Point-source rates (Sect. 2.3, Appendix A) on the 128^3 clumpy medium
+    with 16 sources and 4 bins: HIP events around art_point_sources; the
+    oracle timed on a bounded sample of target cells beside it."""
+    import numpy as np
+    import torch
+    from paper_1410_0763_amd import art, media
+    w = media.point_sources()
+    m = w.medium
+    nb, nz, ny, nx = m.kappa.shape
+    mesh = art.Mesh(nx, ny, nz, m.cell_size)
+    mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+    nab = torch.from_numpy(w.n_abs).cuda()
+    out = mesh.point_sources(w.pos, w.Q, nab, e=w.e, segs=True)
+    torch.cuda.synchronize()
+    segs = int(out["segs"].to(torch.int64).sum().item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        mesh.point_sources(w.pos, w.Q, nab, e=w.e, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rec = {"metric": "segment-bin updates/s of point-source RT (photon-conserving rates)",
+           "value": segs * nb / (ms / 1e3), "unit": "seg-bin updates/s", "n_gpus": 1,
+           "steps": steps, "ms_per_step": ms, "higher_is_better": True, "dtype": "f64 geometry, f32 fields",
+           "data": "synthetic", "segments": segs,
+           "config": {"workload": "128^3 lognormal (sigma_ln 1.5) + 16 opaque spheres, 16 point "
+                                  "sources, 4 bins", "kernel": "art_point_kernel<4>"}}
+    if cpu:
+        from oracle import oracle as O
+        threads = min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        O.point(m.kappa, w.n_abs, w.pos, w.Q, w.e, nthreads=threads)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": segs * nb / dt, "unit": "seg-bin updates/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"the whole workload ({nx * ny * nz} target cells x "
+                                         f"{len(w.pos)} sources x {nb} bins) in {dt:.1f} s"}
+    mesh.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +351,8 @@ def main():
                     help="measure the batched form (48 meshes) instead of the 256^3 sweep")
     ap.add_argument("--surrogate", action="store_true",
                     help="measure the learned surrogate (128^3) instead of the 256^3 sweep")
+    ap.add_argument("--point", action="store_true",
+                    help="measure point-source RT (128^3, 16 sources) instead of the 256^3 sweep")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(*args.traffic_from, sweeps=args.sweeps)
@@ -329,6 +374,9 @@ def main():
         return
     if args.surrogate:
         bench_surrogate()
+        return
+    if args.point:
+        bench_point(steps=args.steps, cpu=not args.no_cpu_baseline)
         return
     m = media.plain_256()
     nb, nz, ny, nx = m.kappa.shape

@@ -75,6 +75,8 @@ struct art_mesh {
     float2 *fields_t = nullptr; size_t fields_t_cap = 0;   // y-fastest copy
     int *bad = nullptr; size_t bad_cap = 0;
     float *stage = nullptr; size_t stage_cap = 0;   // host-upload staging
+    float *kpack = nullptr; size_t kpack_cap = 0;   // kappa h alone (point sources)
+    bool kpack_ok = false;
 
     ArtDir *dirs = nullptr; size_t dirs_cap = 0;
     int *order = nullptr; size_t order_cap = 0;
@@ -99,6 +101,21 @@ struct art_mesh {
 void art_mesh_heating(const art_mesh *m, float hw8[8])
 {
     for (int i = 0; i < 8; ++i) hw8[i] = m->heat[i];
+}
+
+int art_mesh_kpack(art_mesh *m, hipStream_t st, const float **kpack, int *ks)
+{
+    if (m->nb == 0) return fail(ART_E_STATE, "art_set_fields has not been called");
+    const int k = m->nb == 1 ? 1 : (m->nb == 2 ? 2 : 4);
+    if (!m->kpack_ok) {
+        int rc = dev_alloc(&m->kpack, (size_t)m->ncell * k, &m->kpack_cap);
+        if (rc) return rc;
+        HIPCHK(art_launch_kpack(m->fields, m->ncell, m->nb, k, m->kpack, st));
+        m->kpack_ok = true;
+    }
+    *kpack = m->kpack;
+    *ks = k;
+    return ART_OK;
 }
 
 void art_mesh_fields(const art_mesh *m, int dims[3], int *nb, double *h, const float2 **fields)
@@ -399,7 +416,7 @@ int art_destroy_mesh(art_mesh *m)
 {
     if (!m) return ART_OK;
     void *bufs[] = {m->fields, m->fields_t, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
-                    m->state, m->geo, m->acc, m->items, m->desc, m->seg_count};
+                    m->state, m->geo, m->acc, m->items, m->desc, m->seg_count, m->kpack};
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
     for (void *p : bufs)
@@ -419,6 +436,7 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
         if (rc) return rc;
         hipStream_t st = (hipStream_t)hip_stream;
         const size_t n = (size_t)m->ncell * nbins;
+        m->kpack_ok = false;
         if ((rc = dev_alloc(&m->fields, n, &m->fields_cap))) return rc;
         if ((rc = dev_alloc(&m->fields_t, n, &m->fields_t_cap))) return rc;
         if ((rc = dev_alloc(&m->bad, 1, &m->bad_cap))) return rc;

@@ -87,6 +87,12 @@ int art_march_lds_floats(int depth, int nb);
 // Shape, bins, cell size and device field records ([cell][nb] {kappa h,
 // 1/(kappa h), S, 0}; NULL before art_set_fields) of a mesh.
 void art_mesh_fields(const art_mesh *mesh, int dims[3], int *nb, double *h, const float2 **fields);
+// kappa h of every cell without S, ks floats per cell (ks = 1, 2 or 4 for 1,
+// 2 or 3-4 bins; padding 0), built on first use after art_set_fields and
+// kept until the next one.  ART_E_STATE without fields.
+int art_mesh_kpack(art_mesh *mesh, hipStream_t stream, const float **kpack, int *ks);
+hipError_t art_launch_kpack(const float2 *fields, long long ncell, int nb, int ks, float *kpack,
+                            hipStream_t stream);
 
 // float -> bfloat16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t art_bf16_rne(float f)

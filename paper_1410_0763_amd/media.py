@@ -186,6 +186,39 @@ def batch_media(count=48, seed=4000, scale=1.0):
     return media
 
 
+@dataclasses.dataclass
+class PointSources:
+    """Point sources in a medium: positions (nsrc, 3) as (x, y, z) in cell
+    units, photon rates Q (nsrc, nbins), energies above threshold e (nbins,)
+    and the absorber density n_abs (nz, ny, nx), all float64 except n_abs."""
+    medium: Medium
+    pos: np.ndarray
+    Q: np.ndarray
+    e: np.ndarray
+    n_abs: np.ndarray
+
+
+def point_sources(shape=(128, 128, 128), nsrc=16, nbins=4, seed=7000, spheres=16) -> PointSources:
+    """The point-source workload: a lognormal medium (sigma_ln = 1.5) with
+    opaque spheres and nbins bins (kappa_b = kappa0 n x_HI nu_b^-3, x 100 in
+    the spheres; the absorber density is kappa_0 / kappa0, i.e. n x_HI with
+    the spheres' factor, and the cross-section kappa0 nu_b^-3), nsrc
+    sources at uniform random positions, photon rates Q_b ~ nu_b^-2 times a
+    log-uniform luminosity per source, and energies above threshold
+    e_b = nu_b - 1 + 1/8 (units of the threshold energy)."""
+    med = clumpy_medium(shape, nside=1, sigma_ln=1.5, seed=seed, nbins=nbins, spheres=spheres,
+                        name=f"point_{shape[0]}")
+    rng = _rng(seed + 50)
+    nz, ny, nx = shape
+    pos = rng.uniform(0.0, 1.0, size=(nsrc, 3)) * np.array([nx, ny, nz], dtype=np.float64)
+    nu = 1.0 + np.arange(nbins) / 4.0
+    lum = 10.0 ** rng.uniform(-1.0, 1.0, size=nsrc)
+    Q = lum[:, None] * nu[None, :] ** -2.0
+    e = nu - 1.0 + 0.125
+    n_abs = (med.kappa[0].astype(np.float64) / 0.5).astype(np.float32)
+    return PointSources(med, pos, Q, e, n_abs)
+
+
 def surrogate_medium(i: int, train=True, shape=(128, 128, 128)) -> Medium:
     """Field i of the surrogate set: lognormal (sigma_ln = 1.5) + 16 spheres, one bin."""
     seed = (5000 if train else 6000) + i

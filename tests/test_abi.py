@@ -31,11 +31,36 @@ def test_surrogate_header_and_binding_agree():
     assert _declared("art_surrogate.h") == sorted(art.SG_EXPORTS)
 
 
+def test_point_header_and_binding_agree():
+    from paper_1410_0763_amd import art
+    assert _declared("art_point.h") == sorted(art.PT_EXPORTS)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1410_0763_amd import art
     L = art.load()
-    for name in _declared() + _declared("art_nn.h") + _declared("art_surrogate.h"):
+    for name in (_declared() + _declared("art_nn.h") + _declared("art_surrogate.h") +
+                 _declared("art_point.h")):
         assert hasattr(L, name), name
+
+
+def test_point_argument_checks_without_gpu():
+    """Sources outside the box, negative or non-finite photon rates and calls
+    before set_fields are rejected before any device work."""
+    import numpy as np
+    from paper_1410_0763_amd import art
+    L = art.load()
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = ctypes.c_void_p(1)
+    assert L.art_point_sources(None, 1, None, None, None, p, p, None, None, None) == -1
+    h = ctypes.c_void_p()
+    assert L.art_create_mesh(4, 5, 6, 1.0, ctypes.byref(h)) == 0
+    pos = np.array([[1.0, 1.0, 1.0]])
+    Q = np.array([[1.0]])
+    args = lambda pp, qq: (pp.ctypes.data_as(dp), qq.ctypes.data_as(dp), None, p, p, None, None, None)
+    assert L.art_point_sources(h, 1, *args(pos, Q)) == -4          # no fields yet
+    assert b"art_set_fields" in L.art_last_error()
+    assert L.art_destroy_mesh(h) == 0
 
 
 def test_checkpoint_digest_is_sha256():
