@@ -330,8 +330,10 @@ struct art_batch {
     ArtMeshDesc *descs = nullptr; size_t descs_cap = 0;
     ArtItem *items = nullptr; size_t items_cap = 0;
     unsigned int *seg_count = nullptr; size_t seg_cap = 0;
-    struct Launch { int off, n, nb, lds, interleave; };
+    struct Launch { int off, n, nb, lds, interleave, chain; };
     std::vector<Launch> launches;
+    std::vector<int> mesh_chain;        // chain (stream of the captured graph) of each mesh
+    int nchain = 1;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -344,23 +346,61 @@ namespace {
 int batch_enqueue(art_batch *B, hipStream_t st)
 {
     const int n = (int)B->meshes.size();
+    // Meshes with different (bins, directions per wave) never share a launch:
+    // each such chain runs on its own stream between a fork and a join, so
+    // that the captured graph lets the chains overlap.
+    std::vector<hipStream_t> side(B->nchain, st);
+    std::vector<hipEvent_t> evs;
+    auto cleanup = [&]() {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        for (hipStream_t s : side)
+            if (s != st) (void)hipStreamDestroy(s);
+    };
+    auto chk = [&](hipError_t e) -> int {
+        if (e != hipSuccess) { cleanup(); return fail(ART_E_HIP, std::string("batch capture: ") + hipGetErrorString(e)); }
+        return ART_OK;
+    };
+    int rc;
+    if (B->nchain > 1) {
+        hipEvent_t fork;
+        if ((rc = chk(hipEventCreateWithFlags(&fork, hipEventDisableTiming)))) return rc;
+        evs.push_back(fork);
+        if ((rc = chk(hipEventRecord(fork, st)))) return rc;
+        for (int c = 0; c < B->nchain; ++c) {
+            hipStream_t s;
+            if ((rc = chk(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)))) return rc;
+            side[c] = s;
+            if ((rc = chk(hipStreamWaitEvent(s, fork, 0)))) return rc;
+        }
+    }
     for (int i = 0; i < n; ++i) {
         art_mesh *m = B->meshes[i];
-        HIPCHK(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
-                               m->tune.subsets, m->dirs, m->order, m->bucket_start, m->geo,
-                               m->desc_host.geo_stride, m->state, m->desc_host.I_bc, st));
+        if ((rc = chk(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
+                                      m->tune.subsets, m->dirs, m->order, m->bucket_start, m->geo,
+                                      m->desc_host.geo_stride, m->state, m->desc_host.I_bc,
+                                      side[B->mesh_chain[i]])))) return rc;
     }
     for (const auto &L : B->launches)
-        HIPCHK(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,
-                                64 * B->waves, B->seg_count + L.off, st));
+        if ((rc = chk(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,
+                                       64 * B->waves, B->seg_count + L.off, side[L.chain])))) return rc;
     for (int i = 0; i < n; ++i) {
         art_mesh *m = B->meshes[i];
         const art_outputs &o = B->outs[i];
-        HIPCHK(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields, m->ncell,
-                                    m->nb, 12 * B->nside[i] * B->nside[i], B->gw[i].data(),
-                                    B->hw[i].data(), o.J_in, o.J, o.J_exact, o.Gamma, o.Heat,
-                                    nullptr, nullptr, st));
+        if ((rc = chk(art_launch_normalize(m->acc, m->bucket_start, 24 * m->tune.subsets, m->fields, m->ncell,
+                                           m->nb, 12 * B->nside[i] * B->nside[i], B->gw[i].data(),
+                                           B->hw[i].data(), o.J_in, o.J, o.J_exact, o.Gamma, o.Heat,
+                                           nullptr, nullptr, side[B->mesh_chain[i]])))) return rc;
     }
+    if (B->nchain > 1) {
+        for (int c = 0; c < B->nchain; ++c) {
+            hipEvent_t j;
+            if ((rc = chk(hipEventCreateWithFlags(&j, hipEventDisableTiming)))) return rc;
+            evs.push_back(j);
+            if ((rc = chk(hipEventRecord(j, side[c])))) return rc;
+            if ((rc = chk(hipStreamWaitEvent(st, j, 0)))) return rc;
+        }
+    }
+    cleanup();
     return ART_OK;
 }
 
@@ -667,6 +707,7 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         // per (wavefront, nb): items of all meshes
         std::map<std::tuple<int, int, int>, std::vector<ArtItem>> groups;
         std::map<std::tuple<int, int, int>, int> lds;
+        std::map<std::pair<int, int>, int> chains;   // (bins, directions per wave) -> chain
         for (int i = 0; i < n; ++i) {
             art_mesh *m = meshes[i];
             int rc = check_mesh_ready(m, nside[i]);
@@ -686,6 +727,12 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
             for (int q = 0; q < 8; ++q) h[q] = m->heat[q];
             B->hw.push_back(h);
             const int lf = art_march_lds_floats(m->tune.depth, m->nb);
+            const auto ck = std::make_pair(m->nb, m->tune.interleave);
+            if (!chains.count(ck)) {
+                const int c = (int)chains.size();
+                chains[ck] = c;
+            }
+            B->mesh_chain.push_back(chains[ck]);
             for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
                 auto key = std::make_tuple((int)w, m->nb, m->tune.interleave);
                 auto &v = groups[key];
@@ -700,10 +747,12 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         std::vector<ArtItem> flat;
         for (auto &kv : groups) {
             art_batch::Launch L{(int)flat.size(), (int)kv.second.size(), std::get<1>(kv.first),
-                                lds[kv.first], std::get<2>(kv.first)};
+                                lds[kv.first], std::get<2>(kv.first),
+                                chains[std::make_pair(std::get<1>(kv.first), std::get<2>(kv.first))]};
             flat.insert(flat.end(), kv.second.begin(), kv.second.end());
             B->launches.push_back(L);
         }
+        B->nchain = (int)chains.size();
         int rc;
         if ((rc = dev_alloc(&B->descs, descs.size(), &B->descs_cap))) { batch_free(B); return rc; }
         if ((rc = dev_alloc(&B->items, flat.size(), &B->items_cap))) { batch_free(B); return rc; }
