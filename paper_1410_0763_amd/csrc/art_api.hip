@@ -314,10 +314,14 @@ int check_mesh_ready(const art_mesh *m, int nside)
 
 // ---------------------------------------------------------------------------
 // Batched form: several meshes (each with its own shape, Nside, bins and
-// tuning) marched by one launch sequence.  Launch (w, nb) holds the
-// wavefront-w items of every mesh with nb bins; items index a descriptor
-// array of all meshes.  The whole sequence is captured once into a hipGraph
-// on an internal stream and replayed on the caller's stream.
+// tuning) marched by one captured graph.  Launch (w, nb, K) holds the
+// wavefront-w items of every mesh with nb bins and K directions per wave;
+// items index a descriptor array of all meshes.  The meshes of one (nb, K)
+// form a chain (direction setup, their launches in wavefront order, their
+// normalisations) on a stream of its own, forked from and joined to the
+// capture stream, so that the replayed graph runs the chains side by side.
+// The graph is captured once on an internal stream and replayed on the
+// caller's stream.
 // ---------------------------------------------------------------------------
 struct art_batch {
     std::vector<art_mesh *> meshes;
