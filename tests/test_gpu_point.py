@@ -130,3 +130,29 @@ def test_workload_128_sampled_cells():
     assert np.all(np.isfinite(got["Gamma"])) and np.all(got["Gamma"] >= 0.0)
     check("point 128 sampled:Gamma", got["Gamma"].ravel()[idx], ref["Gamma"])
     check("point 128 sampled:Heat", got["Heat"].ravel()[idx], ref["Heat"])
+
+
+def test_new_fields_rebuild_the_pack():
+    """The kappa pack follows art_set_fields: new values and a new bin count
+    (1 -> 3 -> 2) each give the oracle's rates for the fields then loaded."""
+    import torch
+    from oracle import oracle as O
+    from paper_1410_0763_amd import art
+    print("\n== case point sources after new fields", flush=True)
+    rng = np.random.default_rng(99)
+    shape = (7, 9, 8)
+    mesh = art.Mesh(shape[2], shape[1], shape[0], 1.0)
+    n_abs = rng.uniform(0.5, 1.5, shape).astype(np.float32)
+    nab = torch.from_numpy(n_abs).cuda()
+    pos = np.array([[1.2, 7.7, 3.3], [6.5, 0.4, 6.9]])
+    for nb in (1, 3, 2):
+        kappa = rng.uniform(0.05, 1.2, (nb,) + shape).astype(np.float32)
+        mesh.set_fields(torch.from_numpy(kappa).cuda(), torch.zeros(kappa.shape).cuda())
+        Q = rng.uniform(0.5, 1.5, (2, nb))
+        e = rng.uniform(0.1, 1.0, nb)
+        out = mesh.point_sources(pos, Q, nab, e=e)
+        torch.cuda.synchronize()
+        ref = O.point(kappa, n_abs, pos, Q, e)
+        check(f"point new fields nb={nb}:Gamma", out["Gamma"].cpu().numpy().ravel(), ref["Gamma"])
+        check(f"point new fields nb={nb}:Heat", out["Heat"].cpu().numpy().ravel(), ref["Heat"])
+    mesh.close()
