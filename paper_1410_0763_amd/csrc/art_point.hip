@@ -42,6 +42,25 @@ struct PtChunk {
     int has_e;
 };
 
+// One step of the cell walk: the segment from t to the nearest plane
+// crossing (its cell, clamped to the mesh, and its length), then the move to
+// the next cell across that plane (ties: x, y, z).
+__device__ __forceinline__ void walk_step(double &tnx, double &tny, double &tnz, double &t, int &cell,
+                                          int dcx, int dcy, int dcz, double dtx, double dty,
+                                          double dtz, int ncell, int &cl, double &dl)
+{
+    const double tmin = fmin(tnx, fmin(tny, tnz));
+    dl = tmin - t;
+    cl = min(max(cell, 0), ncell - 1);
+    t = tmin;
+    const bool mx = tnx == tmin;
+    const bool my = !mx && tny == tmin;
+    cell += mx ? dcx : (my ? dcy : dcz);
+    tnx += mx ? dtx : 0.0;
+    tny += my ? dty : 0.0;
+    tnz += (!mx && !my) ? dtz : 0.0;
+}
+
 // kappa h of the NB bins of one cell from the pack (KS floats per cell).
 template <int NB, int KS>
 __device__ __forceinline__ void load_kh(const float *__restrict__ kp, int cell, float *kh)
@@ -133,31 +152,19 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
         // The walk moves one axis at a time and never back, so it enters the
         // target after exactly nmove = |dix| + |diy| + |diz| moves; segment k
         // runs from the (k-1)-th to the k-th crossing, the last crossing being
-        // r_in.  Four steps of geometry, then their four loads, then their
-        // sums, so that four loads are in flight per lane; steps past nmove
-        // have dl = 0.  The cell index is clamped to the mesh before every
-        // load.
+        // r_in.  Groups of four steps of geometry, then their four loads, then
+        // their sums, so that four loads are in flight per lane; the last
+        // nmove mod 4 steps one by one.  The cell index is clamped to the
+        // mesh before every load.
         const int nmove = abs(cx - ix) + abs(cy - iy) + abs(cz - iz);
         double t = 0.0;
-        for (int k = 0; k < nmove; k += PT_UNROLL) {
+        int k = 0;
+        for (; k + PT_UNROLL <= nmove; k += PT_UNROLL) {
             int cl[PT_UNROLL];
             double dl[PT_UNROLL];
 #pragma unroll
-            for (int u = 0; u < PT_UNROLL; ++u) {
-                const double tmin = fmin(tnx, fmin(tny, tnz));
-                const bool go = k + u < nmove;
-                dl[u] = go ? tmin - t : 0.0;
-                cl[u] = min(max(cell, 0), ncell - 1);
-                t = go ? tmin : t;
-                // the nearest crossing moves the walk to the next cell (ties: x, y, z)
-                const bool mx = go && tnx == tmin;
-                const bool my = go && !mx && tny == tmin;
-                const bool mz = go && !mx && !my;
-                cell += mx ? dcx : (my ? dcy : (mz ? dcz : 0));
-                tnx += mx ? dtx : 0.0;
-                tny += my ? dty : 0.0;
-                tnz += mz ? dtz : 0.0;
-            }
+            for (int u = 0; u < PT_UNROLL; ++u)
+                walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, ncell, cl[u], dl[u]);
             float kh[PT_UNROLL][NB];
 #pragma unroll
             for (int u = 0; u < PT_UNROLL; ++u) load_kh<NB, KS>(kp, cl[u], kh[u]);
@@ -165,6 +172,15 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
             for (int u = 0; u < PT_UNROLL; ++u)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) tau[b] = fma((double)kh[u][b], dl[u], tau[b]);
+        }
+        for (; k < nmove; ++k) {                  // the last nmove mod 4 steps
+            int cl;
+            double dl;
+            walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, ncell, cl, dl);
+            float kh[NB];
+            load_kh<NB, KS>(kp, cl, kh);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) tau[b] = fma((double)kh[b], dl, tau[b]);
         }
         nseg += (unsigned)nmove;
         ++nseg;                                   // the target cell itself
