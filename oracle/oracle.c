@@ -39,6 +39,16 @@
  *   Q5 Gamma = sum_b g_b (J_in_b + S_b) with caller weights g_b: the affine
  *      form of eq gamma_diff with the frequency integral folded into g_b.
  *   Q6 the intensity entering the box is a uniform I_bc.
+ *
+ * Point sources (Sect. 2.3 and Appendix A; oracle_point, oracle_point_pair
+ * at the end of this file) use the same crossing-and-midpoint segment
+ * finder along the line from the source to each cell's centre.  Readings:
+ *   P1 one absorbing species, rates per absorber, frequency integrals as sums
+ *      over the bins with per-bin photon rates Q_b and energies e_b;
+ *   P2 the line runs from the source through the cell's centre; r_in = 0 when
+ *      the source lies in the cell; a source at the centre takes +x;
+ *   P3 the shell r_in..r_out holds n_c (4 pi / 3)(r_out^3 - r_in^3) h^3
+ *      absorbers; tau runs from the source to r_in.
  */
 #include <math.h>
 #include <stdint.h>
