@@ -58,6 +58,29 @@ def load_traffic():
     return t.get("hbm_bytes_per_sweep")
 
 
+POINT_SRC = os.path.join(ROOT, "paper_1410_0763_amd", "csrc", "art_point.hip")
+POINT_VALU_FILE = os.path.join(ROOT, "profiles", "point_128_valu.json")
+# vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave
+# instruction occupies a SIMD for 4 cycles; FP64 and FP32 alike)
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def point_valu_per_segment():
+    """Vector-ALU lane-instructions per segment of the point-source kernel from
+    the committed counter summary, or None when absent or taken on another
+    kernel source."""
+    try:
+        with open(POINT_VALU_FILE) as f:
+            t = json.load(f)
+        with open(POINT_SRC, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if t.get("point_source_sha256_16") != h:
+        return None
+    return t.get("valu_lane_instructions_per_segment")
+
+
 COPY_BYTES = 1 << 30   # calibration copy: 1 GiB read + 1 GiB written
 
 
@@ -321,6 +344,12 @@ def bench_point(steps=5, cpu=True):
            "data": "synthetic", "segments": segs,
            "config": {"workload": "128^3 lognormal (sigma_ln 1.5) + 16 opaque spheres, 16 point "
                                   "sources, 4 bins", "kernel": "art_point_kernel<4>"}}
+    vps = point_valu_per_segment()
+    if vps is not None:
+        achieved = vps * segs / (ms / 1e3)
+        rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_LANE_PEAK,
+                           "unit": "vector lane-instructions/s", "frac": achieved / VALU_LANE_PEAK,
+                           "valu_per_segment": vps, "traffic": None}
     if cpu:
         from oracle import oracle as O
         threads = min(16, os.cpu_count() or 1)
