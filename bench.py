@@ -208,7 +208,7 @@ def bench_batched(count=48, replays=5):
     print(json.dumps(rec), flush=True)
 
 
-def bench_surrogate(train_fields=16, steps=800):
+def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
     """128^3, Nside 2 -> 16: time of coarse sweep + network inference against
     the fine sweep, held-out errors, and the conv layer's matrix-core rate."""
     import torch
@@ -228,7 +228,7 @@ def bench_surrogate(train_fields=16, steps=800):
             mesh.set_fields(k, s)
             t = torch.zeros(V, dtype=torch.float32, device="cuda")
             w = torch.zeros(V, dtype=torch.float32, device="cuda")
-            Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w)
+            Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w, lam=lam)
             out.append(dict(k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf))
         return out
     train = pairs(range(train_fields), True)
@@ -301,7 +301,7 @@ def bench_surrogate(train_fields=16, steps=800):
     rec = {"metric": "surrogate: coarse sweep + inference time against the fine sweep (128^3, Nside 2 -> 16)",
            "value": fine_ms / sur_ms, "unit": "x faster than the fine sweep",
            "surrogate_ms": sur_ms, "fine_sweep_ms": fine_ms, "coarse_sweep_ms": coarse_ms,
-           "inference_ms": infer_ms, "train_steps": steps, "train_s": train_s,
+           "inference_ms": infer_ms, "train_steps": steps, "train_s": train_s, "loss_lambda": lam,
            "held_out_log_rms": {"coarse": float(np.mean(lr_c)), "surrogate": float(np.mean(lr_s))},
            "held_out_rel_l2": {"coarse": float(np.mean(l2_c)), "surrogate": float(np.mean(l2_s))},
            "params": model.n_params(),
