@@ -73,3 +73,27 @@ def test_adamw_first_step_is_signed_lr():
     g = np.array([0.3, -0.1, 0.0])
     w1, m, v = R.adamw(w, g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=1e-12)
     np.testing.assert_allclose(w1, w - 0.01 * np.sign(g), atol=1e-10)
+
+
+def test_adamw_weight_decay_is_decoupled():
+    """Decoupled weight decay (Loshchilov & Hutter): the decay term lr wd w is
+    added to the step outside the adaptive moments.  With a constant gradient
+    the bias-corrected moments are exactly g and g^2, so every step is
+    w <- w (1 - lr wd) - lr g / (|g| + eps), a closed-form recurrence."""
+    w0 = np.array([1.0, -2.0, 0.5, 3.0])
+    g = np.array([0.3, -0.1, 0.0, 2.0])
+    lr, wd, eps = 0.05, 0.4, 1e-12
+    w, m, v = w0.copy(), np.zeros(4), np.zeros(4)
+    expect = w0.copy()
+    for step in range(1, 6):
+        w, m, v = R.adamw(w, g, m, v, step, lr=lr, eps=eps, wd=wd)
+        expect = expect * (1 - lr * wd) - lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(w, expect, rtol=1e-12, atol=1e-14)
+    # the moments do not see the decay
+    _, m0, v0 = R.adamw(w0, g, np.zeros(4), np.zeros(4), 1, lr=lr, eps=eps, wd=0.0)
+    _, m1, v1 = R.adamw(w0, g, np.zeros(4), np.zeros(4), 1, lr=lr, eps=eps, wd=wd)
+    np.testing.assert_array_equal(m0, m1)
+    np.testing.assert_array_equal(v0, v1)
+    # with zero gradient only the decay acts: w (1 - lr wd) exactly
+    wz, _, _ = R.adamw(w0, np.zeros(4), np.zeros(4), np.zeros(4), 1, lr=lr, eps=1e-8, wd=wd)
+    np.testing.assert_allclose(wz, w0 * (1 - lr * wd), rtol=1e-15)
