@@ -79,7 +79,8 @@ typedef struct {
  * Ownership: *out is owned by the library until art_destroy_mesh. */
 int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out);
 
-/* Release the mesh and all its device memory (NULL is accepted). */
+/* Release the mesh and all its device memory (NULL is accepted).
+ * ART_E_STATE, and nothing is released, while a live batch holds the mesh. */
 int art_destroy_mesh(art_mesh *mesh);
 
 /* Load the absorption coefficient kappa (>= 0, finite) and source function S
@@ -87,7 +88,11 @@ int art_destroy_mesh(art_mesh *mesh);
  * float32, from device memory (on_device = 1) or host memory (on_device = 0).
  * The library copies and re-lays out the data (Sect. 3: mesh data are moved to
  * the accelerator before the sweep); the caller keeps ownership of its arrays.
- * Synchronises hip_stream to report invalid values (ART_E_INVAL). */
+ * The values are checked before anything is written, and hip_stream is
+ * synchronised to report invalid ones: ART_E_INVAL leaves the mesh with the
+ * fields it had (a mesh with valid fields stays ready to sweep).  While a
+ * live batch holds the mesh, a different bin count gives ART_E_STATE (new
+ * values of the same bin count are fine: later replays use them). */
 int art_set_fields(art_mesh *mesh, int nbins, const float *kappa, const float *S,
                    int on_device, void *hip_stream);
 
@@ -106,7 +111,11 @@ int art_set_heating(art_mesh *mesh, const float *heat_in, const float *heat_src)
 /* Full sweep over the 12 nside^2 HEALPix directions (Sect. 2.2-2.3).
  * gamma_w: host array [nbins] of rate weights (NULL = all 1).  I_bc: uniform
  * intensity entering the box (Sect. 3.1 casts rays from the boundaries).
- * out: caller-owned device buffers (see art_outputs). */
+ * out: caller-owned device buffers (see art_outputs).  The direction tables
+ * of the last (nside, direction range, I_bc) are kept on the device and
+ * reused.  Buffers grow on the first sweep at a larger Nside (this
+ * synchronises the device); while a live batch holds the mesh such a sweep
+ * gives ART_E_STATE instead. */
 int art_sweep(art_mesh *mesh, int nside, const float *gamma_w, float I_bc,
               const art_outputs *out, void *hip_stream);
 
@@ -129,7 +138,8 @@ int art_sweep_stats(art_mesh *mesh, long long *segments, float *march_ms, float 
 
 /* Launch-shape control.  art_set_tuning validates and stores t for later
  * sweeps of this mesh (ART_E_INVAL if outside the limits, ART_E_UNSUPPORTED if
- * the block's accumulators exceed the workgroup's local memory). */
+ * the block's accumulators exceed the workgroup's local memory, ART_E_STATE
+ * while a live batch holds the mesh). */
 int art_set_tuning(art_mesh *mesh, const art_tuning *t);
 int art_get_tuning(const art_mesh *mesh, art_tuning *t);
 
@@ -140,7 +150,8 @@ int art_get_tuning(const art_mesh *mesh, art_tuning *t);
  * and return it in *best and its sweep time in *best_ms (either may be NULL).
  * Candidates the mesh cannot run (local-memory limit) are skipped; on error
  * the mesh keeps its previous tuning.  Synchronises hip_stream and holds a
- * scratch output of nbins x cells floats while it runs. */
+ * scratch output of nbins x cells floats while it runs.  ART_E_STATE while a
+ * live batch holds the mesh. */
 int art_autotune(art_mesh *mesh, int nside, const art_tuning *candidates, int ncand,
                  art_tuning *best, float *best_ms, void *hip_stream);
 
@@ -150,12 +161,18 @@ int art_autotune(art_mesh *mesh, int nside, const art_tuning *candidates, int nc
  * every mesh.  nside[i], gamma_w[i] (host array of the mesh's bins, or NULL),
  * outs[i] (caller-owned device buffers, which must outlive the batch) as in
  * art_sweep; exit sums are not produced (outs[i].exit_sum is ignored).  waves:
- * waves per workgroup for all meshes, 1..8.  art_batch_create runs no sweep;
- * art_batch_launch replays the graph on hip_stream (asynchronous);
- * art_batch_stats synchronises with the last launch and returns the segment-
- * bin updates it performed and its HIP-event time.  The meshes must not be
- * re-tuned, re-filled with a different bin count or destroyed while the batch
- * exists (their buffers are captured in the graph). */
+ * waves per workgroup for all meshes, 1..8.  art_batch_create runs no sweep:
+ * it builds each mesh's direction tables on hip_stream and synchronises it;
+ * the graph holds the march launches and the normalisations.
+ * art_batch_launch replays the graph on hip_stream (asynchronous), first
+ * rebuilding the tables of any mesh that a plain sweep at another Nside,
+ * range or I_bc has used since; art_batch_stats synchronises with the last
+ * launch and returns the segment-bin updates it performed and its HIP-event
+ * time.  The meshes' buffers are captured in the graph, so while the batch
+ * exists each mesh refuses (ART_E_STATE) whatever would reallocate or
+ * re-shape them: re-tuning, autotuning, a different bin count, a sweep at a
+ * larger Nside, and art_destroy_mesh.  Work on one mesh queued on two streams
+ * at once races. */
 typedef struct art_batch art_batch;
 int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const float *const *gamma_w,
                      float I_bc, const art_outputs *outs, int waves, art_batch **out,
@@ -163,6 +180,20 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
 int art_batch_launch(art_batch *batch, void *hip_stream);
 int art_batch_stats(art_batch *batch, long long *segment_bins, float *ms);
 int art_batch_destroy(art_batch *batch);
+
+/* The block-wavefront schedule a sweep of an nx x ny x nz mesh with launch
+ * shape t runs (host only, no device work; Sect. 3.1 and 3.3: single writers
+ * without atomics, each block after the blocks its rays come from).  Work
+ * item q is (wavefront w, block, bucket): items[3q..3q+2].  Buckets are
+ * (a * 8 + octant) * subsets + subset for dominant axis a (x = 0, y = 1,
+ * z = 2) and octant bit i set when the rays travel towards decreasing x_i;
+ * block = (pa * nbc + pc) * nbb + pb indexes the 8 x 8 x depth blocks along
+ * (a, c, b), b < c the other two axes, nbb, nbc the block counts along b, c.
+ * Launch w of a sweep runs the items of wavefront w.  *n = item count,
+ * *nwave = wavefront count (may be NULL); items may be NULL to query n,
+ * else it must hold cap >= n triples (ART_E_INVAL otherwise). */
+int art_schedule(int nx, int ny, int nz, const art_tuning *t, int *items, long long cap,
+                 long long *n, int *nwave);
 
 /* Number of directions of an Nside (12 nside^2), or ART_E_INVAL. */
 int art_ndirs(int nside);

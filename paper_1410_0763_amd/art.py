@@ -22,7 +22,7 @@ MAX_NSIDE = 64
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
-           "art_ndirs", "art_last_error", "art_autotune", "art_set_heating")
+           "art_ndirs", "art_last_error", "art_autotune", "art_set_heating", "art_schedule")
 # include/art_nn.h: layers of the learned surrogate
 NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
     L.art_set_heating.argtypes = [vp, vp, vp]
     L.art_autotune.argtypes = [vp, i, ctypes.POINTER(Tuning), i, ctypes.POINTER(Tuning),
                                ctypes.POINTER(ctypes.c_float), vp]
+    L.art_schedule.argtypes = [i, i, i, ctypes.POINTER(Tuning), vp, ctypes.c_longlong,
+                               ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i)]
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
@@ -166,8 +168,9 @@ class Mesh:
         self.nbins = 0
 
     def close(self):
+        """Free the mesh (ArtError ART_E_STATE, mesh kept, while a live batch holds it)."""
         if getattr(self, "_h", None):
-            load().art_destroy_mesh(self._h)
+            _check(load().art_destroy_mesh(self._h))
             self._h = None
 
     def __del__(self):
@@ -318,6 +321,21 @@ class Mesh:
         _check(load().art_sweep_range(self._h, nside, d_begin, d_end, float(I_bc), _ptr(A1),
                                       _ptr(A2), _stream_ptr(stream)))
         return A1, A2
+
+
+def schedule(shape_xyz, depth=6, subsets=1, waves=1, interleave=3):
+    """The block-wavefront schedule of a sweep (art_schedule, host only):
+    (items int32 [n, 3] of (wavefront, block, bucket), number of wavefronts)."""
+    import numpy as np
+    nx, ny, nz = shape_xyz
+    t = Tuning(depth, subsets, waves, interleave)
+    n = ctypes.c_longlong()
+    nw = ctypes.c_int()
+    _check(load().art_schedule(nx, ny, nz, ctypes.byref(t), None, 0, ctypes.byref(n), ctypes.byref(nw)))
+    items = np.zeros((n.value, 3), dtype=np.int32)
+    _check(load().art_schedule(nx, ny, nz, ctypes.byref(t), ctypes.c_void_p(items.ctypes.data),
+                               n.value, ctypes.byref(n), ctypes.byref(nw)))
+    return items, nw.value
 
 
 class Batch:

@@ -96,6 +96,25 @@ struct art_mesh {
     ArtMeshDesc *desc = nullptr; size_t desc_cap = 0;
     ArtMeshDesc desc_host{};
     bool desc_valid = false;
+
+    // Direction tables (dirs, order, bucket_start, crossing table and the
+    // boundary slots of the state buffer) depend only on this key; a sweep
+    // whose key matches the tables on the device skips the generator.
+    struct TableKey {
+        int nside = 0, d_begin = 0, d_end = 0, subsets = 0, nb = 0;
+        float I_bc = 0.0f;
+        bool operator==(const TableKey &o) const
+        {
+            return nside == o.nside && d_begin == o.d_begin && d_end == o.d_end &&
+                   subsets == o.subsets && nb == o.nb &&
+                   std::memcmp(&I_bc, &o.I_bc, sizeof I_bc) == 0;
+        }
+    };
+    TableKey tab{};
+    bool tab_valid = false;
+    // Live batches holding this mesh: its buffers are captured in their
+    // graphs, so nothing may reallocate them, re-tune the mesh or free it.
+    int batches = 0;
 };
 
 void art_mesh_heating(const art_mesh *m, float hw8[8])
@@ -149,18 +168,15 @@ int validate_tuning(const art_tuning &t, int nb)
 // Work items of the block wavefronts.  For dominant axis a the blocks are
 // 8 x 8 columns (axes b < c) by `depth` cells along a; launch w holds, for
 // every (a, octant) group, the blocks whose indices counted along the group's
-// travel directions sum to w, once per direction subset.
-int build_schedule(art_mesh *m)
+// travel directions sum to w, once per direction subset.  Host only.
+void schedule_items(const int N[3], int depth, int subsets, std::vector<ArtItem> &flat,
+                    std::vector<int> &wave_off)
 {
-    const art_tuning &t = m->tune;
-    const int key[6] = {m->nx, m->ny, m->nz, t.depth, t.subsets, 2};
-    if (m->items && std::equal(key, key + 6, m->sched_key)) return ART_OK;
-    const int N[3] = {m->nx, m->ny, m->nz};
     std::vector<std::vector<ArtItem>> waves;
     for (int a = 0; a < 3; ++a) {
         const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
         int nblk[3];
-        nblk[a] = nblocks(N[a], t.depth);
+        nblk[a] = nblocks(N[a], depth);
         nblk[b] = nblocks(N[b], 8);
         nblk[c] = nblocks(N[c], 8);
         const int W = nblk[0] + nblk[1] + nblk[2] - 2;
@@ -175,16 +191,26 @@ int build_schedule(art_mesh *m)
                         for (int ax = 0; ax < 3; ++ax)
                             wsum += ((o >> ax) & 1) ? nblk[ax] - 1 - p[ax] : p[ax];
                         const int blk = (pa * nblk[c] + pc) * nblk[b] + pb;
-                        for (int s = 0; s < t.subsets; ++s)
-                            waves[wsum].push_back(ArtItem{0, blk, (a * 8 + o) * t.subsets + s, 0});
+                        for (int s = 0; s < subsets; ++s)
+                            waves[wsum].push_back(ArtItem{0, blk, (a * 8 + o) * subsets + s, 0});
                     }
     }
-    std::vector<ArtItem> flat;
-    m->wave_off.assign(1, 0);
+    flat.clear();
+    wave_off.assign(1, 0);
     for (auto &w : waves) {
         flat.insert(flat.end(), w.begin(), w.end());
-        m->wave_off.push_back((int)flat.size());
+        wave_off.push_back((int)flat.size());
     }
+}
+
+int build_schedule(art_mesh *m)
+{
+    const art_tuning &t = m->tune;
+    const int key[6] = {m->nx, m->ny, m->nz, t.depth, t.subsets, 2};
+    if (m->items && std::equal(key, key + 6, m->sched_key)) return ART_OK;
+    const int N[3] = {m->nx, m->ny, m->nz};
+    std::vector<ArtItem> flat;
+    schedule_items(N, t.depth, t.subsets, flat, m->wave_off);
     HIPCHK(hipDeviceSynchronize());   // items of earlier sweeps may still be in use
     int rc = dev_alloc(&m->items, flat.size(), &m->items_cap);
     if (rc) return rc;
@@ -240,14 +266,25 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
         (long long)nd * std::max(m->nx, std::max(m->ny, m->nz)) * 16 >= (1ll << 31))
         return fail(ART_E_UNSUPPORTED, "mesh too large for 32-bit offsets within a bucket of directions or a block");
     const int nbk = 24 * m->tune.subsets;
+    const int gstride = std::max(m->nx, std::max(m->ny, m->nz));
+    const size_t need_state = (size_t)state_bound(m, nd), need_geo = (size_t)nd * gstride;
+    const size_t need_acc = (size_t)nbk * m->nb * 2 * m->ncell;
+    if (m->batches > 0 &&
+        ((size_t)nd > m->dirs_cap || (size_t)nd > m->order_cap || (size_t)nbk + 1 > m->bs_cap ||
+         need_state > m->state_cap || need_geo > m->geo_cap || need_acc > m->acc_cap))
+        return fail(ART_E_STATE, "this sweep would reallocate buffers of a mesh held by a live batch "
+                                 "(larger Nside than the batch's); destroy the batch first");
+    const void *tab_bufs[5] = {m->dirs, m->order, m->bucket_start, m->state, m->geo};
     int rc;
     if ((rc = dev_alloc(&m->dirs, (size_t)nd, &m->dirs_cap))) return rc;
     if ((rc = dev_alloc(&m->order, (size_t)nd, &m->order_cap))) return rc;
     if ((rc = dev_alloc(&m->bucket_start, (size_t)nbk + 1, &m->bs_cap))) return rc;
-    if ((rc = dev_alloc(&m->state, (size_t)state_bound(m, nd), &m->state_cap))) return rc;
-    const int gstride = std::max(m->nx, std::max(m->ny, m->nz));
-    if ((rc = dev_alloc(&m->geo, (size_t)nd * gstride, &m->geo_cap))) return rc;
-    if ((rc = dev_alloc(&m->acc, (size_t)nbk * m->nb * 2 * m->ncell, &m->acc_cap))) return rc;
+    if ((rc = dev_alloc(&m->state, need_state, &m->state_cap))) return rc;
+    if ((rc = dev_alloc(&m->geo, need_geo, &m->geo_cap))) return rc;
+    if ((rc = dev_alloc(&m->acc, need_acc, &m->acc_cap))) return rc;
+    if (tab_bufs[0] != m->dirs || tab_bufs[1] != m->order || tab_bufs[2] != m->bucket_start ||
+        tab_bufs[3] != m->state || tab_bufs[4] != m->geo)
+        m->tab_valid = false;   // new buffers hold no tables
     if ((rc = build_schedule(m))) return rc;
     ArtMeshDesc d{};
     d.fields = m->fields;
@@ -259,7 +296,9 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     d.bucket_start = m->bucket_start;
     d.geo = m->geo;
     d.geo_stride = gstride;
-    d.geo_rows = (long long)nd * gstride;
+    // the whole allocation, not this Nside's rows: switching between Nsides
+    // that fit then leaves the descriptor (and the host) alone
+    d.geo_rows = (long long)m->geo_cap;
     d.interleave = m->tune.interleave;
     d.ncell = m->ncell;
     d.nx = m->nx; d.ny = m->ny; d.nz = m->nz; d.nb = m->nb;
@@ -278,6 +317,33 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     return ART_OK;
 }
 
+art_mesh::TableKey table_key(const art_mesh *m, int nside, int d_begin, int d_end, float I_bc)
+{
+    art_mesh::TableKey k;
+    k.nside = nside;
+    k.d_begin = d_begin;
+    k.d_end = d_end;
+    k.subsets = m->tune.subsets;
+    k.nb = m->nb;
+    k.I_bc = I_bc;
+    return k;
+}
+
+// Direction generator, state offsets with boundary slots, crossing table:
+// queued on st unless the device already holds the tables of this key.
+int ensure_tables(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStream_t st)
+{
+    const art_mesh::TableKey k = table_key(m, nside, d_begin, d_end, I_bc);
+    if (m->tab_valid && m->tab == k) return ART_OK;
+    m->tab_valid = false;
+    HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
+                           m->dirs, m->order, m->bucket_start, m->geo, m->desc_host.geo_stride,
+                           m->state, I_bc, st));
+    m->tab = k;
+    m->tab_valid = true;
+    return ART_OK;
+}
+
 int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStream_t st,
               bool fill_state = false)
 {
@@ -287,9 +353,7 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
     if (!m->ev[0])
         for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&m->ev[i]));
     HIPCHK(hipEventRecord(m->ev[0], st));
-    HIPCHK(art_launch_dirs(nside, m->nx, m->ny, m->nz, m->nb, d_begin, d_end, m->tune.subsets,
-                           m->dirs, m->order, m->bucket_start, m->geo, m->desc_host.geo_stride,
-                           m->state, I_bc, st));
+    if ((rc = ensure_tables(m, nside, d_begin, d_end, I_bc, st))) return rc;
     HIPCHK(hipEventRecord(m->ev[1], st));
     const int lds_floats = art_march_lds_floats(m->tune.depth, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
@@ -343,6 +407,7 @@ struct art_batch {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool launched = false;
+    bool held = false;                  // the meshes count this batch in art_mesh::batches
 };
 
 namespace {
@@ -377,13 +442,8 @@ int batch_enqueue(art_batch *B, hipStream_t st)
             if ((rc = chk(hipStreamWaitEvent(s, fork, 0)))) return rc;
         }
     }
-    for (int i = 0; i < n; ++i) {
-        art_mesh *m = B->meshes[i];
-        if ((rc = chk(art_launch_dirs(B->nside[i], m->nx, m->ny, m->nz, m->nb, 0, 12 * B->nside[i] * B->nside[i],
-                                      m->tune.subsets, m->dirs, m->order, m->bucket_start, m->geo,
-                                      m->desc_host.geo_stride, m->state, m->desc_host.I_bc,
-                                      side[B->mesh_chain[i]])))) return rc;
-    }
+    // (the direction tables are not part of the graph: art_batch_create
+    // builds them and art_batch_launch rebuilds those a plain sweep replaced)
     for (const auto &L : B->launches)
         if ((rc = chk(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,
                                        64 * B->waves, B->seg_count + L.off, side[L.chain])))) return rc;
@@ -411,6 +471,8 @@ int batch_enqueue(art_batch *B, hipStream_t st)
 void batch_free(art_batch *B)
 {
     if (!B) return;
+    if (B->held)
+        for (art_mesh *m : B->meshes) --m->batches;
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     if (B->cap) (void)hipStreamDestroy(B->cap);
@@ -432,6 +494,39 @@ int art_ndirs(int nside)
 {
     if (nside < 1 || nside > ART_MAX_NSIDE) return fail(ART_E_INVAL, "nside out of range");
     return 12 * nside * nside;
+}
+
+int art_schedule(int nx, int ny, int nz, const art_tuning *t, int *items, long long cap,
+                 long long *n, int *nwave)
+{
+    try {
+        if (!t || !n) return fail(ART_E_INVAL, "schedule: null argument");
+        if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+            return fail(ART_E_INVAL, "mesh sides must be in [1, 4096]");
+        int rc = validate_tuning(*t, 1);
+        if (rc) return rc;
+        const int N[3] = {nx, ny, nz};
+        std::vector<ArtItem> flat;
+        std::vector<int> off;
+        schedule_items(N, t->depth, t->subsets, flat, off);
+        *n = (long long)flat.size();
+        if (nwave) *nwave = (int)off.size() - 1;
+        if (items) {
+            if (cap < (long long)flat.size()) return fail(ART_E_INVAL, "schedule: cap below the item count");
+            for (size_t w = 0; w + 1 < off.size(); ++w)
+                for (int q = off[w]; q < off[w + 1]; ++q) {
+                    items[3 * (size_t)q] = (int)w;
+                    items[3 * (size_t)q + 1] = flat[q].block;
+                    items[3 * (size_t)q + 2] = flat[q].bucket;
+                }
+        }
+        g_err.clear();
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
 }
 
 int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out)
@@ -459,6 +554,7 @@ int art_create_mesh(int nx, int ny, int nz, double cell_size, art_mesh **out)
 int art_destroy_mesh(art_mesh *m)
 {
     if (!m) return ART_OK;
+    if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch; destroy the batch first");
     void *bufs[] = {m->fields, m->fields_t, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
                     m->state, m->geo, m->acc, m->items, m->desc, m->seg_count, m->kpack};
     for (hipEvent_t e : m->ev)
@@ -478,11 +574,12 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
             return fail(ART_E_UNSUPPORTED, "nbins must be in [1, " + std::to_string(ART_MAX_BINS) + "]");
         int rc = validate_tuning(m->tune, nbins);
         if (rc) return rc;
+        if (m->batches > 0 && nbins != m->nb)
+            return fail(ART_E_STATE, "mesh is held by a live batch: its bin count cannot change");
         hipStream_t st = (hipStream_t)hip_stream;
         const size_t n = (size_t)m->ncell * nbins;
-        m->kpack_ok = false;
-        if ((rc = dev_alloc(&m->fields, n, &m->fields_cap))) return rc;
-        if ((rc = dev_alloc(&m->fields_t, n, &m->fields_t_cap))) return rc;
+        if (m->batches > 0 && (n > m->fields_cap || n > m->fields_t_cap))
+            return fail(ART_E_STATE, "mesh is held by a live batch: its field buffers cannot grow");
         if ((rc = dev_alloc(&m->bad, 1, &m->bad_cap))) return rc;
         const float *dk = kappa, *ds = S;
         if (!on_device) {
@@ -492,15 +589,17 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
             dk = m->stage;
             ds = m->stage + n;
         }
-        HIPCHK(hipMemsetAsync(m->bad, 0, sizeof(int), st));
-        HIPCHK(art_launch_layout(dk, ds, m->nx, m->ny, m->nz, nbins, m->h, m->fields, m->fields_t, m->bad, st));
+        // validate first: a rejected call leaves the mesh's fields as they were
+        HIPCHK(art_launch_fill(reinterpret_cast<float *>(m->bad), 1, 0.0f, st));
+        HIPCHK(art_launch_check(dk, ds, (long long)n, m->bad, st));
         int bad = 0;
         HIPCHK(hipMemcpyAsync(&bad, m->bad, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (bad) {
-            m->nb = 0;
-            return fail(ART_E_INVAL, "kappa must be finite and >= 0 and S finite in every cell");
-        }
+        if (bad) return fail(ART_E_INVAL, "kappa must be finite and >= 0 and S finite in every cell");
+        m->kpack_ok = false;
+        if ((rc = dev_alloc(&m->fields, n, &m->fields_cap))) return rc;
+        if ((rc = dev_alloc(&m->fields_t, n, &m->fields_t_cap))) return rc;
+        HIPCHK(art_launch_layout(dk, ds, m->nx, m->ny, m->nz, nbins, m->h, m->fields, m->fields_t, st));
         if (m->nb != nbins) {
             m->desc_valid = false;
             for (float &w : m->heat) w = 0.0f;   // weights belong to the old bins
@@ -595,6 +694,7 @@ int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_
     try {
         int rc = check_mesh_ready(m, nside);
         if (rc) return rc;
+        if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch: it cannot be re-tuned");
         std::vector<art_tuning> list;
         if (cand) {
             if (ncand < 1) return fail(ART_E_INVAL, "autotune: ncand must be positive");
@@ -642,6 +742,7 @@ int art_set_tuning(art_mesh *m, const art_tuning *t)
     if (!m || !t) return fail(ART_E_INVAL, "null argument");
     int rc = validate_tuning(*t, m->nb);
     if (rc) return rc;
+    if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch: it cannot be re-tuned");
     m->tune = *t;
     m->desc_valid = false;
     g_err.clear();
@@ -719,6 +820,8 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
             for (int j = 0; j < i; ++j)
                 if (meshes[j] == m) { batch_free(B); return fail(ART_E_INVAL, "batch: a mesh appears twice"); }
             if ((rc = prepare(m, nside[i], I_bc, st))) { batch_free(B); return rc; }
+            const int ndi = 12 * nside[i] * nside[i];
+            if ((rc = ensure_tables(m, nside[i], 0, ndi, I_bc, st))) { batch_free(B); return rc; }
             descs.push_back(m->desc_host);
             B->meshes.push_back(m);
             B->nside.push_back(nside[i]);
@@ -782,6 +885,11 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         B->graph = g;
         e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
+        // the tables queued on the caller's stream are done before any replay
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("batch setup: ") + hipGetErrorString(e)); }
+        for (art_mesh *m : B->meshes) ++m->batches;
+        B->held = true;
         *out = B;
         g_err.clear();
         return ART_OK;
@@ -799,6 +907,12 @@ int art_batch_launch(art_batch *B, void *hip_stream)
     if (!B || !B->exec) return fail(ART_E_INVAL, "batch is NULL");
     hipStream_t st = (hipStream_t)hip_stream;
     HIPCHK(hipEventRecord(B->ev[0], st));
+    // tables that a plain sweep of a mesh replaced since the last replay
+    for (size_t i = 0; i < B->meshes.size(); ++i) {
+        const int ndi = 12 * B->nside[i] * B->nside[i];
+        int rc = ensure_tables(B->meshes[i], B->nside[i], 0, ndi, B->I_bc, st);
+        if (rc) return rc;
+    }
     HIPCHK(hipGraphLaunch(B->exec, st));
     HIPCHK(hipEventRecord(B->ev[1], st));
     B->launched = true;

@@ -23,13 +23,27 @@
 
 namespace {
 
+// Validation pass (before anything is written): bad[0] = 1 if some kappa is
+// negative or not finite, or some S is not finite.
+__global__ __launch_bounds__(256) void art_check_kernel(const float *__restrict__ kappa,
+                                                        const float *__restrict__ S, long long n,
+                                                        int *__restrict__ bad)
+{
+    bool ok = true;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float k = kappa[i], s = S[i];
+        ok = ok && (k >= 0.0f) && isfinite(k) && isfinite(s);
+    }
+    if (!ok) *bad = 1;
+}
+
 __global__ __launch_bounds__(256) void art_layout_kernel(const float *__restrict__ kappa,
                                                          const float *__restrict__ S,
                                                          long long ncell, int nb, float h,
                                                          int nx, int ny, int nz,
                                                          float2 *__restrict__ fields,
-                                                         float2 *__restrict__ fields_t,
-                                                         int *__restrict__ bad)
+                                                         float2 *__restrict__ fields_t)
 {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -38,7 +52,6 @@ __global__ __launch_bounds__(256) void art_layout_kernel(const float *__restrict
     for (int b = 0; b < nb; ++b) {
         const float k = kappa[(long long)b * ncell + c];
         const float s = S[(long long)b * ncell + c];
-        if (!(k >= 0.0f) || !isfinite(k) || !isfinite(s)) *bad = 1;
         const float kh = k * h;
         fields[c * nb + b] = make_float2(kh, s);
         fields_t[ct * nb + b] = make_float2(kh, s);
@@ -134,14 +147,22 @@ __global__ __launch_bounds__(256) void art_exit_sum_kernel(const ArtDir *__restr
 
 }  // namespace
 
+hipError_t art_launch_check(const float *kappa, const float *S, long long n, int *bad_flag,
+                            hipStream_t stream)
+{
+    const long long blocks = std::max<long long>(1, std::min<long long>((n + 255) / 256, 8192));
+    hipLaunchKernelGGL(art_check_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, kappa, S, n,
+                       bad_flag);
+    return hipGetLastError();
+}
+
 hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny, int nz, int nb,
-                             double h, float2 *fields, float2 *fields_t, int *bad_flag,
-                             hipStream_t stream)
+                             double h, float2 *fields, float2 *fields_t, hipStream_t stream)
 {
     const long long ncell = (long long)nx * ny * nz;
     const long long nblk = (ncell + 255) / 256;
     hipLaunchKernelGGL(art_layout_kernel, dim3((unsigned)nblk), dim3(256), 0, stream, kappa, S,
-                       ncell, nb, (float)h, nx, ny, nz, fields, fields_t, bad_flag);
+                       ncell, nb, (float)h, nx, ny, nz, fields, fields_t);
     return hipGetLastError();
 }
 

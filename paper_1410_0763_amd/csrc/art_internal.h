@@ -40,7 +40,7 @@ struct ArtMeshDesc {
     const uint4 *geo;          // [N_d][geo_stride] slab crossing table
     long long ncell;
     int geo_stride;            // max(nx, ny, nz)
-    long long geo_rows;        // rows of the crossing table (N_d * geo_stride)
+    long long geo_rows;        // rows allocated for the crossing table (>= N_d * geo_stride)
     int interleave;            // directions marched together by one wave (1..4)
     int nx, ny, nz, nb;
     int depth;                 // block cells along the dominant axis
@@ -66,9 +66,10 @@ hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begi
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,
                             hipStream_t stream);
+hipError_t art_launch_check(const float *kappa, const float *S, long long n, int *bad_flag,
+                            hipStream_t stream);
 hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny, int nz, int nb,
-                             double h, float2 *fields, float2 *fields_t, int *bad_flag,
-                             hipStream_t stream);
+                             double h, float2 *fields, float2 *fields_t, hipStream_t stream);
 hipError_t art_launch_normalize(const float *acc, const int *bucket_start, int nbuckets,
                                 const float2 *fields, long long ncell, int nb, int nd,
                                 const float *gw4, const float *hw8, float *J_in, float *J,
