@@ -17,7 +17,9 @@ summary was taken on a different march kernel source.
 
 cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
 bounded sample of the same workload: 36 of the 768 directions (around the
-equator) over the full mesh and all four bins.
+equator) over the full mesh and all four bins on every core of the process's
+CPU share (at most 16), and 2 directions on one core (`value_1core`); `nproc`
+and the CPU share are reported with it.
 """
 from __future__ import annotations
 
@@ -143,19 +145,32 @@ def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, sweeps):
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline(medium, d_range=(366, 402)):
+def cpu_baseline(medium, d_range=(366, 402), d_range_1=(366, 368)):
+    """The FP64 oracle on this host's cores: on every core of the process's
+    CPU share (at most 16, the share of one GPU) over 36 directions, and on
+    one core over 2 of them; the rate is work-additive over directions."""
     import numpy as np
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(16, share))
     k = medium.kappa.astype(np.float64)
     s = medium.S.astype(np.float64)
-    t0 = time.perf_counter()
-    r = O.sweep_raw(k, s, medium.nside, d_range=d_range, nthreads=threads)
-    dt = time.perf_counter() - t0
-    units = r["nseg"] * medium.nbins
+
+    def run(rng, nthreads):
+        t0 = time.perf_counter()
+        r = O.sweep_raw(k, s, medium.nside, d_range=rng, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        return r["nseg"] * medium.nbins, dt
+
+    units, dt = run(d_range, threads)
+    units1, dt1 = run(d_range_1, 1)
     return {"value": units / dt, "unit": "seg-bin updates/s", "cores": threads, "kind": "oracle",
             "sample": f"directions {d_range[0]}..{d_range[1] - 1} of 768, full 256^3 mesh, "
-                      f"4 bins ({units:.3e} segment-bin updates in {dt:.1f} s)"}
+                      f"4 bins ({units:.3e} segment-bin updates in {dt:.1f} s on {threads} threads)",
+            "nproc": os.cpu_count(), "cpu_share": share,
+            "value_1core": units1 / dt1,
+            "sample_1core": f"directions {d_range_1[0]}..{d_range_1[1] - 1}, full mesh, 4 bins "
+                            f"({units1:.3e} segment-bin updates in {dt1:.1f} s on 1 thread)"}
 
 
 def bench_batched(count=48, replays=5):
