@@ -107,6 +107,66 @@ def test_conv_gradients_match_reference():
         assert torch.equal(dw, dw2)
 
 
+U32 = 2.0 ** -24      # unit roundoff of float32
+
+
+@pytest.mark.parametrize("cin", [16, 32])
+def test_conv_multitile_elementwise(cin):
+    """Forward, input gradient and weight gradient on a mesh of 3 tiles of 16
+    rows (the last ragged) by 2 tiles of 32 voxels along x, element by
+    element against the FP64 reference: each error within the float32
+    accumulation bound n u sum|terms| (n terms summed, u = 2^-24; the
+    products of bf16 operands are exact), plus one bf16 rounding (2^-8
+    relative) where the output is bf16."""
+    _case(f"conv3d multi-tile cin {cin} shape (3, 40, 64)")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    D, H, W = 3, 40, 64
+    shape = (D, H, W)
+    V = D * H * W
+    rng = np.random.default_rng(100 + cin)
+    xb = bf16_bits(rng.normal(size=(D, H, W, cin)))
+    gb = bf16_bits(rng.normal(size=(D, H, W, 32)))
+    w = (rng.normal(size=(27, cin, 32)) * 0.2).astype(np.float32)
+    bias = (rng.normal(size=32) * 0.1).astype(np.float32)
+    xq, gq, wq = bf16_value(xb), bf16_value(gb), bf16_value(bf16_bits(w))
+    wf = torch.zeros((27, 32, cin), dtype=torch.int16, device="cuda")
+    wbw = torch.zeros((27, 32, 32), dtype=torch.int16, device="cuda")
+    nn.prep_weights(_dev(w), cin, wf, wbw)
+    # forward: channel 0 in float32
+    y0 = torch.zeros(V, dtype=torch.float32, device="cuda")
+    nn.conv3d_fwd(_dev(xb), cin, wf, _dev(bias), shape, 0, y0=y0)
+    # gradients
+    g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
+    nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g, gcf)
+    xs = torch.zeros((3, cin, V), dtype=torch.int16, device="cuda")
+    nn.shift3(_dev(xb.reshape(V, cin)), cin, shape, xs)
+    nchunk = 8
+    part = torch.zeros(nchunk * 27 * cin * 32, dtype=torch.float32, device="cuda")
+    dw = torch.zeros((27, cin, 32), dtype=torch.float32, device="cuda")
+    nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw)
+    dx = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dx)
+    torch.cuda.synchronize()
+
+    ref_y = R.conv3d(xq, wq, bias)[..., 0]
+    abs_y = R.conv3d(np.abs(xq), np.abs(wq), np.abs(bias))[..., 0]
+    got_y = y0.cpu().numpy().reshape(D, H, W).astype(np.float64)
+    ey = np.abs(got_y - ref_y) / (27 * cin + 1) / U32 / abs_y
+    rdx, rdw, _ = R.conv3d_backward(xq, wq, gq)
+    adx, adw, _ = R.conv3d_backward(np.abs(xq), np.abs(wq), np.abs(gq))
+    got_dw = dw.cpu().numpy().astype(np.float64)
+    edw = np.abs(got_dw - rdw) / (V * U32 * np.maximum(adw, 1e-300))
+    got_dx = bf16_value(dx.cpu().numpy()).reshape(D, H, W, 32)[..., :cin]
+    bound_dx = 2.0 ** -8 * np.abs(rdx) + 27 * 32 * U32 * adx
+    edx = np.abs(got_dx - rdx) / np.maximum(bound_dx, 1e-300)
+    print(f"cin {cin}: forward {ey.max():.3f}, dw {edw.max():.3f}, dx {edx.max():.3f} "
+          f"of their bounds; forward max |err|/sum|terms| {np.max(np.abs(got_y - ref_y) / abs_y):.2e}",
+          flush=True)
+    assert ey.max() <= 1.0 and edw.max() <= 1.0 and edx.max() <= 1.0
+
+
 def test_relu_grad_mse_and_adamw():
     _case("relu gradient, mse, adamw")
     import torch
