@@ -216,16 +216,27 @@ __global__ __launch_bounds__(256) void art_geo_kernel(const ArtDir *__restrict__
         if (shb) fb = fmin(1.0, fmax(0.0, ((double)(shb > 0 ? Bb + 1 : Bb) - xb0) * rtb));
         if (shc) fc = fmin(1.0, fmax(0.0, ((double)(shc > 0 ? Bc + 1 : Bc) - xc0) * rtc));
         const bool b_first = fb <= fc;
+        // lengths differenced in double, then rounded: each carries a relative
+        // error of one float rounding, also a sliver next to a crossing (a
+        // float difference of rounded depths would carry an absolute 2^-24,
+        // which a bright ray crossing the sliver turns into a large relative
+        // error of the cell's sums)
         float s1, s2, s3;
         if (shb && shc) {
-            const float f1 = (float)fmin(fb, fc), f2 = (float)fmax(fb, fc);
-            s1 = f1; s2 = f2 - f1; s3 = 1.0f - f2;
+            const double f1 = fmin(fb, fc), f2 = fmax(fb, fc);
+            s1 = (float)f1; s2 = (float)(f2 - f1); s3 = (float)(1.0 - f2);
         } else if (shb || shc) {
-            const float f1 = (float)(shb ? fb : fc);
-            s1 = f1; s2 = 1.0f - f1; s3 = 0.0f;
+            const double f1 = shb ? fb : fc;
+            s1 = (float)f1; s2 = (float)(1.0 - f1); s3 = 0.0f;
         } else {
             s1 = 1.0f; s2 = 0.0f; s3 = 0.0f;
         }
+        // crossings within 1e-12 of each other or of the slab face are one
+        // point in exact arithmetic (a ray through a cell edge): the sliver
+        // between them is a contact of zero length, as in the oracle
+        if (s1 < 1e-12f) s1 = 0.0f;
+        if (s2 < 1e-12f) s2 = 0.0f;
+        if (s3 < 1e-12f) s3 = 0.0f;
         const unsigned npos = (s1 > 0.f) + (s2 > 0.f) + (s3 > 0.f);
         // moves in slab order: 0 none, 1 a b-plane, 2 a c-plane
         const unsigned mv1 = shb && (b_first || !shc) ? 1u : (shc ? 2u : 0u);

@@ -59,7 +59,7 @@
 //   x = kappa h dL,  phi = (1 - e^{-x}) / x,
 //   A1 += ds * I * phi        (sum_j dtau_j Ibar_in,j / sum_j dtau_j per direction)
 //   A2 += ds * (1 - phi)      (exact path average of the source term)
-//   I  <- I + (S - I) x phi   (= I e^{-x} + S (1 - e^{-x}))
+//   I  <- I e^{-x} + S x phi  (x phi = 1 - e^{-x}; two positive terms)
 // For x >= 1/8, phi ds = (1 - e^{-x}) |n_a| / (kappa h) with e^{-x} from
 // v_exp_f32; for x < 1/8, (1 - phi) ds = x q(x) ds from the series of
 // q(x) = (x - 1 + e^{-x}) / x^2 to third order (relative truncation below
@@ -191,7 +191,8 @@ __device__ __forceinline__ void segment(const float *kh, const float *Sv, const 
     for (int b = 0; b < NB; ++b) {
         const float y = kh[b] * dsl;                     // -x log2(e)
         // large-x branch
-        const float e1l = 1.0f - __builtin_amdgcn_exp2f(y);
+        const float el = __builtin_amdgcn_exp2f(y);     // e^{-x}
+        const float e1l = 1.0f - el;
         const float lphil = e1l * fw[b];
         const float lpsil = ds - lphil;
         // small-x branch (truncation below 7e-7 relative for x < 1/8)
@@ -203,9 +204,14 @@ __device__ __forceinline__ void segment(const float *kh, const float *Sv, const 
         const float lpsi = small ? lpsis : lpsil;
         // 1 - e^{-x} = x phi = (phi ds) (kappa h / |n_a|) in either branch
         const float e1 = lphi * ifw[b];
+        // e^{-x}: from the exponential where it may be small, 1 - (1 - e^{-x})
+        // where it is above 0.88; both terms of the update are then positive
+        // (the form I + (S - I)(1 - e^{-x}) cancels when a bright ray enters
+        // an opaque cell)
+        const float e = small ? 1.0f - e1 : el;
         a1[b] = fmaf(I[b], lphi, a1[b]);
         a2[b] += lpsi;
-        I[b] = fmaf(Sv[b] - I[b], e1, I[b]);
+        I[b] = fmaf(I[b], e, Sv[b] * e1);
     }
 }
 

@@ -102,3 +102,88 @@ def test_batch_48_full_size_sampled_cells():
     batch.close()
     for mesh in meshes:
         mesh.close()
+
+
+def _subset_directions(nside):
+    """The first direction of every (dominant axis, octant) group that has one,
+    plus a spread of directions whose dominant axis is tied (reading Q2)."""
+    from oracle import oracle as O
+    n = O.directions(nside)
+    first, ties = {}, []
+    for d in range(len(n)):
+        g = O.dir_geom(nside, d)
+        octant = int(n[d, 0] < 0) | (int(n[d, 1] < 0) << 1) | (int(n[d, 2] < 0) << 2)
+        first.setdefault((g["a"], octant), d)
+        a = np.abs(n[d])
+        if np.count_nonzero(a >= a.max() - 1e-12) > 1:
+            ties.append(d)
+    picks = set(first.values()) | set(ties[:: max(1, len(ties) // 4)])
+    return sorted(picks), len(first), len(ties)
+
+
+def test_plain_256_direction_subset_every_cell():
+    """The benchmark's 256^3 x 4-bin field, direction by direction over a
+    subset that holds every (dominant axis, octant) group and tied
+    directions: the raw sums A1, A2 of art_sweep_range against the oracle's
+    sweep_raw on every cell (Sect. 2.2, eqs rt to averaged_intensity)."""
+    import os
+    import torch
+    from oracle import oracle as O
+    from paper_1410_0763_amd import art
+    m = media.plain_256()
+    dirs, ngroups, nties = _subset_directions(m.nside)
+    print(f"\n== case plain_256 direction subset: {len(dirs)} directions "
+          f"({ngroups} groups, {nties} tied in the set)", flush=True)
+    assert ngroups == 24
+    nb, nz, ny, nx = m.kappa.shape
+    k64 = m.kappa.astype(np.float64)
+    s64 = m.S.astype(np.float64)
+    nthreads = min(16, os.cpu_count() or 1)
+    shp = (nb, nz, ny, nx)
+    with art.Mesh(nx, ny, nz, m.cell_size) as mesh:
+        mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        A1 = torch.empty(shp, device="cuda")
+        A2 = torch.empty(shp, device="cuda")
+        worst = 0.0
+        for d in dirs:
+            mesh.sweep_range(m.nside, d, d + 1, A1=A1, A2=A2)
+            g1 = A1.cpu().numpy()
+            g2 = A2.cpu().numpy()
+            r = O.sweep_raw(k64, s64, m.nside, h=m.cell_size, d_range=(d, d + 1), nthreads=nthreads)
+            s1 = check(f"plain_256 dir {d}:A1", g1, r["jin_sum"])
+            s2 = check(f"plain_256 dir {d}:A2", g2, r["ex_sum"])
+            worst = max(worst, s1["max"], s2["max"])
+        print(f"worst over {len(dirs)} directions: {worst:.3e}", flush=True)
+
+
+def test_plain_256_photon_balance_and_bitwise_repeat():
+    """Properties of the whole 256^3 x 4-bin sweep at any size: two sweeps are
+    bitwise equal, and per bin the absorbed minus emitted photons balance the
+    escaping ones: h sum_c kappa_c (S_c - J_exact,c) = (1/N_d) sum_d |n_a|
+    sum_rays I_exit (I_bc = 0), to within the parity bar (1e-5) of the terms."""
+    import torch
+    from oracle import oracle as O
+    from paper_1410_0763_amd import art
+    m = media.plain_256()
+    print("\n== case plain_256 photon balance and repeat", flush=True)
+    nb, nz, ny, nx = m.kappa.shape
+    with art.Mesh(nx, ny, nz, m.cell_size) as mesh:
+        mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        mesh.set_heating(m.heat_in, m.heat_src)
+        o1 = {k: v.cpu().numpy() for k, v in mesh.sweep(m.nside, gamma_w=m.gamma_w, exit_sum=True).items()}
+        o2 = {k: v.cpu().numpy() for k, v in mesh.sweep(m.nside, gamma_w=m.gamma_w, exit_sum=True).items()}
+        torch.cuda.synchronize()
+    for key in o1:
+        assert np.array_equal(o1[key], o2[key]), f"repeat differs in {key}"
+    nd = O.ndirs(m.nside)
+    w = np.array([O.dir_geom(m.nside, d)["w"] for d in range(nd)])
+    for b in range(nb):
+        kb = m.kappa[b].astype(np.float64)
+        je = o1["J_exact"][b].astype(np.float64)
+        lhs = m.cell_size * np.sum(kb * (m.S[b].astype(np.float64) - je))
+        ex = o1["exit_sum"][:, b].astype(np.float64)
+        rhs = np.sum(w * ex) / nd
+        tol = 1e-5 * (m.cell_size * np.sum(kb * np.abs(je)) + np.sum(w * np.abs(ex)) / nd)
+        print(f"bin {b}: absorbed - emitted {lhs:.6e}, escaping {rhs:.6e}, "
+              f"|diff| {abs(lhs - rhs):.3e} (bound {tol:.3e})", flush=True)
+        assert abs(lhs - rhs) <= tol
