@@ -65,6 +65,7 @@ POINT_VALU_FILE = os.path.join(ROOT, "profiles", "point_128_valu.json")
 # vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave
 # instruction occupies a SIMD for 4 cycles; FP64 and FP32 alike)
 VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, FP64 vector (an FMA counts 2)
 
 
 def point_valu_per_segment():
@@ -359,12 +360,19 @@ def bench_point(steps=5, cpu=True):
            "data": "synthetic", "segments": segs,
            "config": {"workload": "128^3 lognormal (sigma_ln 1.5) + 16 opaque spheres, 16 point "
                                   "sources, 4 bins", "kernel": "art_point_kernel<4>"}}
+    # the method's FP64 work per walk segment (Sect. 2.3): the nearest of the
+    # three next plane crossings (2 comparisons), the segment length (1), the
+    # next crossing of the axis crossed (1), and tau_b += kappa_b h dl per bin
+    # (one fused multiply-add = 2 flops each); against the FP64 vector peak
+    flops_per_seg = 4 + 2 * nb
+    achieved = flops_per_seg * segs / (ms / 1e3) / 1e12
+    rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                       "flops_per_segment": flops_per_seg, "traffic": None}
     vps = point_valu_per_segment()
-    if vps is not None:
-        achieved = vps * segs / (ms / 1e3)
-        rec["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_LANE_PEAK,
-                           "unit": "vector lane-instructions/s", "frac": achieved / VALU_LANE_PEAK,
-                           "valu_per_segment": vps, "traffic": None}
+    if vps is not None:           # measured issue, for reference (not the roofline)
+        rec["valu_lane_instructions_per_segment"] = vps
+        rec["valu_issue_frac"] = vps * segs / (ms / 1e3) / VALU_LANE_PEAK
     if cpu:
         from oracle import oracle as O
         threads = min(16, os.cpu_count() or 1)

@@ -20,11 +20,18 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
-def test_committed_summaries_match_the_sources():
+def test_committed_traffic_summary_matches_the_march_source():
     traffic = bench.load_traffic()
     assert traffic is not None and traffic > 1e11        # bytes per 256^3 sweep
-    vps = bench.point_valu_per_segment()
-    assert vps is not None and 10.0 < vps < 100.0
+
+
+def test_point_roofline_is_algorithmic():
+    """The point-source roofline counts the method's FP64 operations per walk
+    segment (not the kernel's own instruction count) against the FP64 peak."""
+    import inspect
+    src = inspect.getsource(bench.bench_point)
+    assert "flops_per_seg = 4 + 2 * nb" in src
+    assert bench.FP64_VECTOR_PEAK_TFLOPS == pytest.approx(78.6)
 
 
 def test_summaries_of_other_sources_are_ignored(tmp_path, monkeypatch):
