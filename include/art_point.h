@@ -57,6 +57,27 @@ int art_point_sources(art_mesh *mesh, int nsrc, const double *pos, const double 
                       const double *e, const float *n_abs, float *Gamma, float *Heat,
                       unsigned *segs, void *hip_stream);
 
+/* Room of the static scratch of art_point_sources_noalloc, in floats (64 MiB). */
+#define ART_POINT_NOALLOC_FLOATS (16ll * 1024 * 1024)
+
+/*
+ * art_point_sources for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight time-step loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, but the library
+ * calls no hipMalloc, hipFree or allocating routine.  The per-cell kappa
+ * pack the walk reads (1, 2 or 4 floats per cell for 1, 2 or 3-4 bins) is
+ * rebuilt on every call in a static device array of ART_POINT_NOALLOC_FLOATS
+ * floats, one per GPU, which the GPU holds from the first call on it until
+ * the process ends; a mesh whose pack does not fit gives ART_E_UNSUPPORTED
+ * (about 128^3 cells with 4 bins fit).  The mesh's fields must be set
+ * (art_set_fields) beforehand; the caller owns n_abs and the outputs.  All
+ * calls on one GPU share the array: calls that overlap on one GPU (two
+ * streams, two threads) race and give wrong results.
+ */
+int art_point_sources_noalloc(art_mesh *mesh, int nsrc, const double *pos, const double *Q,
+                              const double *e, const float *n_abs, float *Gamma, float *Heat,
+                              unsigned *segs, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

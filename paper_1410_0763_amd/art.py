@@ -35,7 +35,7 @@ SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_
               "art_surrogate_train_step", "art_surrogate_infer", "art_surrogate_param",
               "art_surrogate_save", "art_surrogate_load", "art_sweep_surrogate", "art_sha256")
 # include/art_point.h: rates from point sources
-PT_EXPORTS = ("art_point_sources",)
+PT_EXPORTS = ("art_point_sources", "art_point_sources_noalloc")
 
 
 class ArtError(RuntimeError):
@@ -129,6 +129,7 @@ def load(path: str = LIB_PATH):
     L.art_sweep_surrogate.argtypes = [vp, vp, i, i, vp, f, ctypes.POINTER(Outputs), ip, fp, vp]
     L.art_sha256.argtypes = [vp, ctypes.c_ulonglong, vp]
     L.art_point_sources.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.art_point_sources_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
     for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS:
         if name != "art_last_error":
             getattr(L, name).restype = i
@@ -288,11 +289,13 @@ class Mesh:
                                       ctypes.byref(sms)))
         return dict(segments=seg.value, march_ms=mms.value, sweep_ms=sms.value)
 
-    def point_sources(self, pos, Q, n_abs, e=None, out=None, segs: bool = False, stream=None):
+    def point_sources(self, pos, Q, n_abs, e=None, out=None, segs: bool = False, stream=None,
+                      noalloc: bool = False):
         """Photon-conserving rates per absorber from point sources
-        (art_point_sources): pos (nsrc, 3) and Q (nsrc, nbins) host arrays,
-        e (nbins,) or None, n_abs a device float32 tensor of the mesh's shape.
-        Returns (and fills) a dict Gamma, Heat (and segs) of device tensors."""
+        (art_point_sources, or art_point_sources_noalloc with noalloc=True):
+        pos (nsrc, 3) and Q (nsrc, nbins) host arrays, e (nbins,) or None,
+        n_abs a device float32 tensor of the mesh's shape.  Returns (and
+        fills) a dict Gamma, Heat (and segs) of device tensors."""
         import numpy as np
         import torch
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
@@ -305,7 +308,8 @@ class Mesh:
             if segs:
                 out["segs"] = torch.empty(self.shape, dtype=torch.int32, device="cuda")
         dp = ctypes.POINTER(ctypes.c_double)
-        _check(load().art_point_sources(self._h, nsrc, pos.ctypes.data_as(dp), Q.ctypes.data_as(dp),
+        fn = load().art_point_sources_noalloc if noalloc else load().art_point_sources
+        _check(fn(self._h, nsrc, pos.ctypes.data_as(dp), Q.ctypes.data_as(dp),
                                         None if ev is None else ev.ctypes.data_as(dp),
                                         _ptr(n_abs.contiguous()), _ptr(out["Gamma"]),
                                         _ptr(out.get("Heat")), _ptr(out.get("segs")),

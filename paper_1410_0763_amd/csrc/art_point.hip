@@ -242,9 +242,12 @@ hipError_t art_launch_kpack(const float2 *fields, long long ncell, int nb, int k
     return hipGetLastError();
 }
 
-extern "C" int art_point_sources(art_mesh *mesh, int nsrc, const double *pos, const double *Q,
-                                 const double *e, const float *n_abs, float *Gamma, float *Heat,
-                                 unsigned *segs, void *hip_stream)
+// The entry point's work.  kpack_buf == NULL: the mesh's own kappa pack
+// (built on first use, kept until the next art_set_fields); else the pack is
+// rebuilt into kpack_buf (room for kpack_cap floats) on every call.
+int art_point_impl(art_mesh *mesh, int nsrc, const double *pos, const double *Q, const double *e,
+                   const float *n_abs, float *Gamma, float *Heat, unsigned *segs, void *hip_stream,
+                   float *kpack_buf, long long kpack_cap)
 {
     if (!mesh) return pt_fail(ART_E_INVAL, "art_point_sources: null mesh");
     int dims[3], nb;
@@ -275,8 +278,21 @@ extern "C" int art_point_sources(art_mesh *mesh, int nsrc, const double *pos, co
     hipStream_t st = (hipStream_t)hip_stream;
     const float *kp;
     int ks;
-    int rc = art_mesh_kpack(mesh, st, &kp, &ks);
-    if (rc != ART_OK) return rc;
+    if (kpack_buf) {
+        ks = nb == 1 ? 1 : (nb == 2 ? 2 : 4);
+        const long long ncell = (long long)dims[0] * dims[1] * dims[2];
+        if (ncell * ks > kpack_cap)
+            return pt_fail(ART_E_UNSUPPORTED, "art_point_sources_noalloc: the kappa pack needs " +
+                                                  std::to_string(ncell * ks) + " floats, above the " +
+                                                  std::to_string(kpack_cap) + " of the static scratch");
+        const hipError_t err = art_launch_kpack(rec, ncell, nb, ks, kpack_buf, st);
+        if (err != hipSuccess)
+            return pt_fail(ART_E_HIP, std::string("art_point_sources_noalloc: ") + hipGetErrorString(err));
+        kp = kpack_buf;
+    } else {
+        int rc = art_mesh_kpack(mesh, st, &kp, &ks);
+        if (rc != ART_OK) return rc;
+    }
     int s0 = 0;
     do {
         PtChunk chunk{};
@@ -299,4 +315,11 @@ extern "C" int art_point_sources(art_mesh *mesh, int nsrc, const double *pos, co
         s0 += chunk.n;
     } while (s0 < nsrc);
     return ART_OK;
+}
+
+extern "C" int art_point_sources(art_mesh *mesh, int nsrc, const double *pos, const double *Q,
+                                 const double *e, const float *n_abs, float *Gamma, float *Heat,
+                                 unsigned *segs, void *hip_stream)
+{
+    return art_point_impl(mesh, nsrc, pos, Q, e, n_abs, Gamma, Heat, segs, hip_stream, nullptr, 0);
 }
