@@ -155,6 +155,20 @@ int art_get_tuning(const art_mesh *mesh, art_tuning *t);
 int art_autotune(art_mesh *mesh, int nside, const art_tuning *candidates, int ncand,
                  art_tuning *best, float *best_ms, void *hip_stream);
 
+/* Autotuner with a process-wide cache keyed by (shape class, Nside, bins),
+ * the shape class being floor(log2(cells) / 2) (meshes within about a factor
+ * of 4 in cell count share it): a cached shape is set on the mesh without
+ * timing (*cached = 1), else art_autotune runs and its result is cached
+ * (*cached = 0).  best, best_ms, cached may be NULL.  ART_E_STATE while a
+ * live batch holds the mesh.  The cache is shared by all threads. */
+int art_autotune_class(art_mesh *mesh, int nside, const art_tuning *candidates, int ncand,
+                       art_tuning *best, float *best_ms, int *cached, void *hip_stream);
+
+/* The autotune cache as a text file: op 0 clears it (path unused), 1 writes
+ * it to path, 2 merges the entries of path into it (ART_E_INVAL, the cache
+ * unchanged, for a file that is not a cache or holds an invalid entry). */
+int art_tune_cache(int op, const char *path);
+
 /* Batched form: one launch sequence for n distinct meshes (each already
  * holding fields, each with its own shape, Nside, bins and tuning), captured
  * once into a HIP graph.  Launch w of the sequence marches wavefront w of

@@ -22,7 +22,8 @@ MAX_NSIDE = 64
 EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
-           "art_ndirs", "art_last_error", "art_autotune", "art_set_heating", "art_schedule")
+           "art_ndirs", "art_last_error", "art_autotune", "art_set_heating", "art_schedule",
+           "art_autotune_class", "art_tune_cache")
 # include/art_nn.h: layers of the learned surrogate
 NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(ctypes.c_float), vp]
     L.art_schedule.argtypes = [i, i, i, ctypes.POINTER(Tuning), vp, ctypes.c_longlong,
                                ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(i)]
+    L.art_autotune_class.argtypes = [vp, i, ctypes.POINTER(Tuning), i, ctypes.POINTER(Tuning),
+                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i), vp]
+    L.art_tune_cache.argtypes = [i, ctypes.c_char_p]
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
@@ -253,6 +257,21 @@ class Mesh:
             os.replace(tmp, cache_path)
         return dict(rec, cached=False)
 
+    def autotune_class(self, nside: int, candidates=None, stream=None) -> dict:
+        """art_autotune_class: the launch shape of this mesh's shape class,
+        Nside and bins from the library's cache, or timed and cached."""
+        cands, n = None, 0
+        if candidates:
+            n = len(candidates)
+            cands = (Tuning * n)(*[Tuning(c["depth"], c["subsets"], c["waves"], c["interleave"])
+                                   for c in candidates])
+        best = Tuning()
+        ms = ctypes.c_float()
+        cached = ctypes.c_int()
+        _check(load().art_autotune_class(self._h, nside, cands, n, ctypes.byref(best),
+                                         ctypes.byref(ms), ctypes.byref(cached), _stream_ptr(stream)))
+        return dict(tuning=best.as_dict(), sweep_ms=ms.value, cached=bool(cached.value))
+
     # -- sweeps ----------------------------------------------------------
     def alloc_outputs(self, nside: int, exit_sum: bool = False, device="cuda"):
         import torch
@@ -325,6 +344,12 @@ class Mesh:
         _check(load().art_sweep_range(self._h, nside, d_begin, d_end, float(I_bc), _ptr(A1),
                                       _ptr(A2), _stream_ptr(stream)))
         return A1, A2
+
+
+def tune_cache(op: str, path=None):
+    """The library's autotune cache: op "clear", "save" or "load" (a text file)."""
+    code = {"clear": 0, "save": 1, "load": 2}[op]
+    _check(load().art_tune_cache(code, None if path is None else str(path).encode()))
 
 
 def schedule(shape_xyz, depth=6, subsets=1, waves=1, interleave=3):

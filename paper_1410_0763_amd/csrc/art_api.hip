@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -734,6 +735,121 @@ int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_
         return done(fail(ART_E_NOMEM, "host allocation failed"));
     } catch (...) {
         return done(fail(ART_E_HIP, "unexpected exception"));
+    }
+}
+
+// Process-wide autotune cache keyed by shape class, Nside and bins.
+namespace {
+struct TuneEntry {
+    art_tuning t;
+    float ms;
+};
+std::mutex g_tune_mu;
+std::map<std::array<int, 3>, TuneEntry> g_tune;
+
+// Shape class: cells counted in factors of 4 (floor(log2(cells) / 2)), so that
+// meshes within a factor of about 4 in size share their launch shape.
+int shape_class(const art_mesh *m)
+{
+    int l = 0;
+    for (long long c = m->ncell; c > 1; c >>= 1) ++l;
+    return l / 2;
+}
+}  // namespace
+
+int art_autotune_class(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_tuning *best,
+                       float *best_ms, int *cached, void *hip_stream)
+{
+    try {
+        int rc = check_mesh_ready(m, nside);
+        if (rc) return rc;
+        if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch: it cannot be re-tuned");
+        const std::array<int, 3> key{shape_class(m), nside, m->nb};
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end() && validate_tuning(it->second.t, m->nb) == ART_OK) {
+                m->tune = it->second.t;
+                m->desc_valid = false;
+                if (best) *best = it->second.t;
+                if (best_ms) *best_ms = it->second.ms;
+                if (cached) *cached = 1;
+                g_err.clear();
+                return ART_OK;
+            }
+        }
+        art_tuning bt{};
+        float ms = 0.0f;
+        if ((rc = art_autotune(m, nside, cand, ncand, &bt, &ms, hip_stream))) return rc;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune[key] = TuneEntry{bt, ms};
+        }
+        if (best) *best = bt;
+        if (best_ms) *best_ms = ms;
+        if (cached) *cached = 0;
+        return ART_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
+    }
+}
+
+int art_tune_cache(int op, const char *path)
+{
+    try {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        if (op == 0) {
+            g_tune.clear();
+            return ART_OK;
+        }
+        if (!path) return fail(ART_E_INVAL, "tune cache: null path");
+        if (op == 1) {
+            FILE *f = std::fopen(path, "w");
+            if (!f) return fail(ART_E_INVAL, std::string("tune cache: cannot write ") + path);
+            std::fprintf(f, "art-tune-cache 1\n");
+            for (const auto &kv : g_tune)
+                std::fprintf(f, "%d %d %d %d %d %d %d %.6g\n", kv.first[0], kv.first[1], kv.first[2],
+                             kv.second.t.depth, kv.second.t.subsets, kv.second.t.waves,
+                             kv.second.t.interleave, (double)kv.second.ms);
+            const bool ok = std::fclose(f) == 0;
+            return ok ? ART_OK : fail(ART_E_INVAL, std::string("tune cache: cannot write ") + path);
+        }
+        if (op == 2) {
+            FILE *f = std::fopen(path, "r");
+            if (!f) return fail(ART_E_INVAL, std::string("tune cache: cannot read ") + path);
+            char magic[32] = {0};
+            int ver = 0;
+            if (std::fscanf(f, "%31s %d", magic, &ver) != 2 || std::strcmp(magic, "art-tune-cache") != 0 ||
+                ver != 1) {
+                std::fclose(f);
+                return fail(ART_E_INVAL, "tune cache: not a cache file");
+            }
+            std::map<std::array<int, 3>, TuneEntry> in;
+            int c, ns, nb, d, sub, w, k;
+            double ms;
+            int n;
+            while ((n = std::fscanf(f, "%d %d %d %d %d %d %d %lf", &c, &ns, &nb, &d, &sub, &w, &k, &ms)) == 8) {
+                art_tuning t{d, sub, w, k};
+                if (validate_tuning(t, nb) != ART_OK || ns < 1 || ns > ART_MAX_NSIDE || nb < 1 || nb > ART_MAX_BINS) {
+                    std::fclose(f);
+                    return fail(ART_E_INVAL, "tune cache: invalid entry");
+                }
+                in[{c, ns, nb}] = TuneEntry{t, (float)ms};
+            }
+            const bool clean_end = n == EOF;
+            std::fclose(f);
+            if (!clean_end) return fail(ART_E_INVAL, "tune cache: malformed line");
+            for (const auto &kv : in) g_tune[kv.first] = kv.second;
+            g_err.clear();
+            return ART_OK;
+        }
+        return fail(ART_E_INVAL, "tune cache: op must be 0 (clear), 1 (save) or 2 (load)");
+    } catch (const std::bad_alloc &) {
+        return fail(ART_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ART_E_HIP, "unexpected exception");
     }
 }
 

@@ -136,3 +136,33 @@ def test_host_only_calls():
     assert L.art_sweep(h, 2, None, ctypes.c_float(0.0), ctypes.byref(o), None) == -4
     assert L.art_destroy_mesh(h) == 0
     assert L.art_destroy_mesh(None) == 0
+
+
+def test_tune_cache_file_round_trip_and_rejections(tmp_path):
+    """The autotune cache file (host only): bad files are rejected with the
+    cache unchanged, a valid file loads and saves back to the same entries."""
+    from paper_1410_0763_amd import art
+    art.tune_cache("clear")
+    good = tmp_path / "good.txt"
+    good.write_text("art-tune-cache 1\n7 8 4 6 1 1 3 101.5\n4 2 1 4 1 1 2 0.75\n")
+    bad_magic = tmp_path / "bad1.txt"
+    bad_magic.write_text("not-a-cache 1\n")
+    bad_entry = tmp_path / "bad2.txt"
+    bad_entry.write_text("art-tune-cache 1\n7 8 4 0 1 1 3 1.0\n")       # depth 0
+    bad_line = tmp_path / "bad3.txt"
+    bad_line.write_text("art-tune-cache 1\n7 8 4 6 1 1\n")
+    for p in (bad_magic, bad_entry, bad_line, tmp_path / "missing.txt"):
+        with pytest.raises(art.ArtError):
+            art.tune_cache("load", p)
+    out = tmp_path / "out.txt"
+    art.tune_cache("save", out)
+    assert out.read_text().splitlines() == ["art-tune-cache 1"]          # still empty
+    art.tune_cache("load", good)
+    art.tune_cache("save", out)
+    lines = sorted(out.read_text().splitlines()[1:])
+    assert lines == ["4 2 1 4 1 1 2 0.75", "7 8 4 6 1 1 3 101.5"]
+    art.tune_cache("clear")
+    with pytest.raises(KeyError):
+        art.tune_cache("frobnicate")
+    L = art.load()
+    assert L.art_tune_cache(7, None) == -1                                 # unknown op

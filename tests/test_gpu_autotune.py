@@ -37,3 +37,46 @@ def test_autotune_parity_and_cache(tmp_path):
         with pytest.raises(art.ArtError):
             mesh.autotune(m.nside, candidates=[big])
         assert mesh.get_tuning() == ok      # unchanged by the failed call
+
+
+def test_autotune_class_cache_shared_by_a_shape_class(tmp_path):
+    """art_autotune_class: the first mesh of a (shape class, Nside, bins) key
+    is timed, a second mesh of the same class takes the cached shape without
+    timing, a saved cache file restores it, and the sweeps at the chosen
+    shapes match the oracle."""
+    print("\n== case autotune by shape class: 20x18x22 and 22x21x19, 2 bins, nside 2", flush=True)
+    import torch
+    from paper_1410_0763_amd import art
+    art.tune_cache("clear")
+    meds = [media.clumpy_medium((22, 18, 20), nside=2, sigma_ln=1.0, seed=61, nbins=2, name="c0"),
+            media.clumpy_medium((19, 21, 22), nside=2, sigma_ln=1.0, seed=62, nbins=2, name="c1")]
+    cands = [dict(depth=d, subsets=1, waves=1, interleave=k) for d in (3, 6) for k in (2, 3)]
+    res = []
+    for i, m in enumerate(meds):
+        nb, nz, ny, nx = m.kappa.shape
+        with art.Mesh(nx, ny, nz) as mesh:
+            mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+            r = mesh.autotune_class(m.nside, candidates=cands)
+            print(r, flush=True)
+            res.append(r)
+            assert mesh.get_tuning() == r["tuning"]
+            out = mesh.sweep(m.nside, gamma_w=m.gamma_w)
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy() for k, v in out.items()}
+            ref = oracle_sweep(m)
+            from gpu_common import check
+            for key in ("J_in", "J_exact", "Gamma"):
+                check(f"{m.name} tuned:{key}", g[key], ref[key])
+    assert not res[0]["cached"] and res[1]["cached"]
+    assert res[1]["tuning"] == res[0]["tuning"]
+    path = tmp_path / "cache.txt"
+    art.tune_cache("save", path)
+    art.tune_cache("clear")
+    art.tune_cache("load", path)
+    m = meds[1]
+    nb, nz, ny, nx = m.kappa.shape
+    with art.Mesh(nx, ny, nz) as mesh:
+        mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+        r = mesh.autotune_class(m.nside, candidates=cands)
+        assert r["cached"] and r["tuning"] == res[0]["tuning"]
+    art.tune_cache("clear")
