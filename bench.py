@@ -260,9 +260,11 @@ def bench_batched(count=48, reps=5):
     print(json.dumps(rec), flush=True)
 
 
-def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
+def bench_surrogate(train_fields=64, steps=4800, lam=1.0, test_fields=8):
     """128^3, Nside 2 -> 16: time of coarse sweep + network inference against
-    the fine sweep, held-out errors, and the conv layer's matrix-core rate."""
+    the fine sweep, held-out errors (the gate's relative L2 of J and the
+    per-cell log error), and the conv layer's matrix-core rate.  Inputs are
+    the coarse sweep's J, the log density and the neutral fraction."""
     import torch
     from paper_1410_0763_amd import art, media
     from paper_1410_0763_amd import surrogate as SG
@@ -281,15 +283,19 @@ def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
             t = torch.zeros(V, dtype=torch.float32, device="cuda")
             w = torch.zeros(V, dtype=torch.float32, device="cuda")
             Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w, lam=lam)
-            out.append(dict(k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf))
+            out.append(dict(k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf,
+                            n=torch.from_numpy(m.density).cuda().reshape(-1),
+                            xh=torch.from_numpy(m.x_hi).cuda().reshape(-1)))
         return out
+    t0 = time.perf_counter()
     train = pairs(range(train_fields), True)
-    model.fit_stats([p["Jc"] for p in train[:2]], [p["k"].reshape(-1) for p in train[:2]],
-                    [p["s"].reshape(-1) for p in train[:2]], margin=1.0)
+    model.fit_stats([p["Jc"] for p in train[:4]], [p["n"] for p in train[:4]],
+                    [p["xh"] for p in train[:4]], margin=1.0)
     for p in train:
         p["x"] = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
-        model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), p["x"])
-    test = pairs(range(4), False)
+        model.features(p["Jc"], p["n"], p["xh"], p["x"])
+    test = pairs(range(test_fields), False)
+    data_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     for it in range(steps):
         lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 1e-5
@@ -301,7 +307,7 @@ def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
     model.set_val_err(0.0)
     for p in test:
         mesh.set_fields(p["k"], p["s"])
-        out, fb, _ = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1e9)
+        out, fb, _ = SG.sweep_surrogate(mesh, model, p["n"], p["xh"], 2, 16, err_bound=1e9)
         J = out["J"].reshape(-1)
         Jf = p["Jf"]
         lr_s.append(torch.sqrt(torch.mean(torch.log(J / Jf) ** 2)).item())
@@ -328,14 +334,14 @@ def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
     used = []
 
     def sur():
-        _, fb, _ = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0, out=sout)
+        _, fb, _ = SG.sweep_surrogate(mesh, model, p["n"], p["xh"], 2, 16, err_bound=1.0, out=sout)
         used.append(fb)
     sur_ms = timed(sur)
     assert not any(used), "the gate fell back during the timed surrogate calls"
     fine_ms = timed(lambda: mesh.sweep(16))
     coarse_ms = timed(lambda: mesh.sweep(2))
     x = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
-    model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), x)
+    model.features(p["Jc"], p["n"], p["xh"], x)
     infer_ms = timed(lambda: model.forward(x))
     # one 32 -> 32 channel layer (the network's dominant kernel) on the trained
     # layer-1 weights and the layer-0 activations of a held-out field
@@ -354,6 +360,8 @@ def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
            "value": fine_ms / sur_ms, "unit": "x faster than the fine sweep",
            "surrogate_ms": sur_ms, "fine_sweep_ms": fine_ms, "coarse_sweep_ms": coarse_ms,
            "inference_ms": infer_ms, "train_steps": steps, "train_s": train_s, "loss_lambda": lam,
+           "train_fields": train_fields, "held_out_fields": test_fields, "data_s": data_s,
+           "inputs": "log J (Nside 2), log n, x_HI; target log(J_in at Nside 16 / J_in at Nside 2)",
            "held_out_log_rms": {"coarse": float(np.mean(lr_c)), "surrogate": float(np.mean(lr_s))},
            "held_out_rel_l2": {"coarse": float(np.mean(l2_c)), "surrogate": float(np.mean(l2_s))},
            "params": model.n_params(),
@@ -361,8 +369,8 @@ def bench_surrogate(train_fields=16, steps=1600, lam=0.1):
                         "achieved": conv_flop / (conv_ms / 1e3) / 1e12, "peak": 2500.0,
                         "unit": "TFLOP/s", "frac": conv_flop / (conv_ms / 1e3) / 1e12 / 2500.0,
                         "layer_ms": conv_ms},
-           "config": {"workload": "128^3 lognormal sigma_ln 1.5 + 16 spheres, 1 bin; 16 training "
-                                  "fields (seeds 5000+i), 4 held-out (6000+i)"}}
+           "config": {"workload": f"128^3 lognormal sigma_ln 1.5 + 16 spheres, 1 bin; {train_fields} "
+                                  f"training fields (seeds 5000+i), {test_fields} held-out (6000+i)"}}
     mesh.close()
     print(json.dumps(rec), flush=True)
 

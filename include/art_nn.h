@@ -86,12 +86,14 @@ int art_nn_adamw(float *w, const float *g, float *m, float *v, int n, float lr, 
                  float beta2, float eps, float wd, int step, void *hip_stream);
 
 /* Surrogate input features, bf16 [V][16]: channel k < 3 is
- * (log(max(f_k, 1e-30)) - mu[k]) * inv_sd[k] for f = (J, kappa, S), the rest
- * 0.  mu, inv_sd: host arrays [3]. */
-int art_nn_features(const float *J, const float *kappa, const float *S, int V, const float *mu,
+ * (f_k - mu[k]) * inv_sd[k] with f_0 = log(max(J, 1e-30)) (J of the coarse
+ * sweep), f_1 = log(max(density, 1e-30)), f_2 = x_hi (neutral fraction), the
+ * rest 0.  J, density, x_hi: device float32 [V]; mu, inv_sd: host arrays [3]. */
+int art_nn_features(const float *J, const float *density, const float *x_hi, int V, const float *mu,
                     const float *inv_sd, void *x, void *hip_stream);
 
-/* J_out = J_coarse * exp(pred): the surrogate predicts log(J_fine / J_coarse). */
+/* J_out = J_coarse * exp(pred) (elementwise; the surrogate predicts the log
+ * ratio of the fine to the coarse incoming mean intensity J_in). */
 int art_nn_expand(const float *J_coarse, const float *pred, int V, float *J_out,
                   void *hip_stream);
 

@@ -9,13 +9,16 @@
  * Network
  * -------
  * Input per cell (bf16 [V][16], channels-last, V = nx*ny*nz, x fastest):
- * (log J_coarse, log kappa, log S) of one frequency bin, each shifted by mu
- * and divided by sd (the surrogate's feature statistics), floored at 1e-30
- * before the logarithm; J_coarse is the mean intensity J (eq
- * mean_intensity) of a sweep at a small Nside.  Six convolution layers (3^3
- * taps, zero padding, 32 channels, ReLU after the first five) predict
- * p = log(J_fine / J_coarse), J_fine being J of a sweep at a large Nside; the
- * estimate is J_coarse e^p.  114,209 trainable parameters.
+ * (log J_coarse, log n, x_HI) of one frequency bin, each shifted by mu and
+ * divided by sd (the surrogate's feature statistics), J_coarse and the
+ * density n floored at 1e-30 before the logarithm; J_coarse is the mean
+ * intensity J (eq mean_intensity) of a sweep at a small Nside, n and x_HI
+ * the density and neutral fraction the caller's kappa and S were made from.
+ * Six convolution layers (3^3 taps, zero padding, 32 channels, ReLU after
+ * the first five) predict p = log(J_in,fine / J_in,coarse), J_in being the
+ * incoming part of J (J = J_in + S) of the sweeps at a large and the small
+ * Nside; the estimate is J_in = J_in,coarse e^p and J = J_in + S (the local
+ * source term is exact at any Nside).  114,209 trainable parameters.
  *
  * Acceptance gate
  * ---------------
@@ -79,26 +82,29 @@ int art_surrogate_set_stats(art_surrogate *s, const float *mu, const float *sd, 
 int art_surrogate_get_stats(const art_surrogate *s, float *mu, float *sd, float *lo, float *hi,
                             float *val_err);
 
-/* Fit mu and sd (mean and population standard deviation) of the three log
- * features over n fields (host arrays of n device pointers to float32 [V]
- * J_coarse, kappa and S of bin 0), and lo, hi = extremes of the normalised
- * features -/+ margin (>= 0).  val_err is left as it is.  Partial sums are
- * double precision, added in a fixed order.  Synchronises hip_stream. */
+/* Fit mu and sd (mean and population standard deviation) of the three raw
+ * features (log J_coarse, log n, x_HI) over n fields (host arrays of n device
+ * pointers to float32 [V] J_coarse, density and neutral fraction), and lo, hi
+ * = extremes of the normalised features -/+ margin (>= 0).  val_err is left
+ * as it is.  Partial sums are double precision, added in a fixed order.
+ * Synchronises hip_stream. */
 int art_surrogate_fit_stats(art_surrogate *s, int n, const float *const *J_coarse,
-                            const float *const *kappa, const float *const *S, float margin,
+                            const float *const *density, const float *const *x_hi, float margin,
                             void *hip_stream);
 
-/* Network input x (bf16 [V][16]) of one field from J_coarse, kappa and S
- * (device float32 [V]) with the current statistics. */
-int art_surrogate_features(const art_surrogate *s, const float *J_coarse, const float *kappa,
-                           const float *S, void *x, void *hip_stream);
+/* Network input x (bf16 [V][16]) of one field from J_coarse, density and
+ * x_HI (device float32 [V]) with the current statistics. */
+int art_surrogate_features(const art_surrogate *s, const float *J_coarse, const float *density,
+                           const float *x_hi, void *x, void *hip_stream);
 
 /* Training pair of the field loaded in mesh (one bin, shape of the
  * surrogate): the sweeps at nside_coarse and nside_fine (I_bc = 0) write
- * J_coarse (required) and J_fine (may be NULL), target = log(J_fine /
- * J_coarse) and, if weight is not NULL, the loss weights
- * (J_coarse^2 / mean J_coarse^2 + lambda) / (1 + lambda), lambda >= 0
- * (art_nn_sq_weights).  All device float32 [V]. */
+ * J_coarse (required; the network's input) and J_fine (may be NULL),
+ * target = log(J_in,fine / J_in,coarse) and, if weight is not NULL, the loss
+ * weights (J_in,coarse^2 / mean J_in,coarse^2 + lambda) / (1 + lambda),
+ * lambda >= 0 (art_nn_sq_weights), which make the loss approximate the
+ * squared relative L2 error of J_in (lambda = 0) or the per-cell squared
+ * log error (large lambda).  All device float32 [V]. */
 int art_surrogate_make_pair(art_surrogate *s, art_mesh *mesh, int nside_coarse, int nside_fine,
                             float lambda, float *target, float *weight, float *J_coarse,
                             float *J_fine, void *hip_stream);
@@ -115,7 +121,7 @@ int art_surrogate_train_step(art_surrogate *s, const void *x, const float *targe
                              const float *weight, float lr, float wd, float *loss,
                              void *hip_stream);
 
-/* Prediction p = log(J_fine / J_coarse) for input x into pred (device
+/* Prediction p = log(J_in,fine / J_in,coarse) for input x into pred (device
  * float32 [V]). */
 int art_surrogate_infer(art_surrogate *s, const void *x, float *pred, void *hip_stream);
 
@@ -134,18 +140,20 @@ int art_surrogate_save(art_surrogate *s, const char *path, void *hip_stream);
 int art_surrogate_load(art_surrogate *s, const char *path, void *hip_stream);
 
 /* J of a sweep at nside_fine from the sweep at nside_coarse and the network,
- * for the field loaded in mesh (one bin, the surrogate's shape, I_bc = 0).
- * If the gate accepts: out->J = J_coarse e^p, out->J_in = J - S,
+ * for the field loaded in mesh (one bin, the surrogate's shape, I_bc = 0)
+ * made from density and x_hi (device float32 [V], the network's inputs).
+ * If the gate accepts: out->J_in = J_in,coarse e^p, out->J = J_in + S,
  * out->Gamma = gamma_w[0] J (gamma_w host [1] or NULL for 1), out->Heat =
  * heat_in[0] J_in + heat_src[0] S (the mesh's weights, art_set_heating) and
  * out->J_exact = J + (J_exact - J) of the coarse sweep (the network predicts
- * J only).  Otherwise out receives art_sweep at nside_fine.  out->exit_sum
- * must be NULL.  *used_fallback (0 or 1) and *est_err (NaN while val_err is
- * unknown) may be NULL.  An err_bound <= 0 always falls back.  Synchronises
- * hip_stream once, to read the out-of-range count. */
-int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int nside_fine,
-                        const float *gamma_w, float err_bound, const art_outputs *out,
-                        int *used_fallback, float *est_err, void *hip_stream);
+ * J_in only).  Otherwise out receives art_sweep at nside_fine.
+ * out->exit_sum must be NULL.  *used_fallback (0 or 1) and *est_err (NaN
+ * while val_err is unknown) may be NULL.  An err_bound <= 0 always falls
+ * back.  Synchronises hip_stream once, to read the out-of-range count. */
+int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, const float *density, const float *x_hi,
+                        int nside_coarse, int nside_fine, const float *gamma_w, float err_bound,
+                        const art_outputs *out, int *used_fallback, float *est_err,
+                        void *hip_stream);
 
 /* SHA-256 (FIPS 180-4) of n bytes at data (host) into digest[32]: the
  * checkpoint digest. */

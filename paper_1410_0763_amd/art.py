@@ -130,7 +130,7 @@ def load(path: str = LIB_PATH):
     L.art_surrogate_param.argtypes = [vp, i, i, vp, i, vp]
     L.art_surrogate_save.argtypes = [vp, cp, vp]
     L.art_surrogate_load.argtypes = [vp, cp, vp]
-    L.art_sweep_surrogate.argtypes = [vp, vp, i, i, vp, f, ctypes.POINTER(Outputs), ip, fp, vp]
+    L.art_sweep_surrogate.argtypes = [vp, vp, vp, vp, i, i, vp, f, ctypes.POINTER(Outputs), ip, fp, vp]
     L.art_sha256.argtypes = [vp, ctypes.c_ulonglong, vp]
     L.art_point_sources.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
     L.art_point_sources_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -475,9 +475,9 @@ class nn:
                                    _stream_ptr(stream)))
 
     @staticmethod
-    def features(J, kappa, S, V, mu, inv_sd, x, stream=None):
-        _check(load().art_nn_features(_ptr(J), _ptr(kappa), _ptr(S), V, nn._f3(mu), nn._f3(inv_sd),
-                                      _ptr(x), _stream_ptr(stream)))
+    def features(J, density, x_hi, V, mu, inv_sd, x, stream=None):
+        _check(load().art_nn_features(_ptr(J), _ptr(density), _ptr(x_hi), V, nn._f3(mu),
+                                      nn._f3(inv_sd), _ptr(x), _stream_ptr(stream)))
 
     @staticmethod
     def expand(J_coarse, pred, V, J_out, stream=None):

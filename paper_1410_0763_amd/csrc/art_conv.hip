@@ -406,13 +406,13 @@ struct F3 {
     float a[3];
 };
 
-__global__ void features_kernel(const float *__restrict__ J, const float *__restrict__ kap,
-                                const float *__restrict__ S, long long V, F3 mu, F3 isd,
+__global__ void features_kernel(const float *__restrict__ J, const float *__restrict__ dens,
+                                const float *__restrict__ xhi, long long V, F3 mu, F3 isd,
                                 uint16_t *__restrict__ x)
 {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    art_feature_store(J[v], kap[v], S[v], mu.a, isd.a, x + v * 16);
+    art_feature_store(J[v], dens[v], xhi[v], mu.a, isd.a, x + v * 16);
 }
 
 __global__ void expand_kernel(const float *__restrict__ Jc, const float *__restrict__ pred,
@@ -593,10 +593,10 @@ int art_nn_adamw(float *w, const float *g, float *m, float *v, int n, float lr, 
     return launch_status("art_nn_adamw");
 }
 
-int art_nn_features(const float *J, const float *kappa, const float *S, int V, const float *mu,
+int art_nn_features(const float *J, const float *density, const float *x_hi, int V, const float *mu,
                     const float *inv_sd, void *x, void *hip_stream)
 {
-    if (!J || !kappa || !S || !mu || !inv_sd || !x || V < 1)
+    if (!J || !density || !x_hi || !mu || !inv_sd || !x || V < 1)
         return art_set_error(ART_E_INVAL, "art_nn_features: bad arguments");
     F3 m3, s3;
     for (int k = 0; k < 3; ++k) {
@@ -604,7 +604,7 @@ int art_nn_features(const float *J, const float *kappa, const float *S, int V, c
         s3.a[k] = inv_sd[k];
     }
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, (hipStream_t)hip_stream,
-                       J, kappa, S, (long long)V, m3, s3, (uint16_t *)x);
+                       J, density, x_hi, (long long)V, m3, s3, (uint16_t *)x);
     return launch_status("art_nn_features");
 }
 

@@ -103,15 +103,23 @@ __device__ __forceinline__ uint16_t art_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Raw surrogate feature k of a value: the logarithm (floored at 1e-30) for
+// k = 0 (J of the coarse sweep) and k = 1 (density), the value itself for
+// k = 2 (neutral fraction, in [0, 1]).
+__device__ __forceinline__ float art_feature_raw(int k, float v)
+{
+    return k < 2 ? logf(fmaxf(v, 1e-30f)) : v;
+}
+
 // Input record of the surrogate network for one cell, 16 bf16 channels:
-// channel k < 3 is (log(max(f_k, 1e-30)) - mu[k]) * isd[k] for
-// f = (J, kappa, S), the other 13 are 0.
-__device__ __forceinline__ void art_feature_store(float J, float kappa, float S, const float *mu,
+// channel k < 3 is (raw feature k - mu[k]) * isd[k] for (J, n, x_HI), the
+// other 13 are 0.
+__device__ __forceinline__ void art_feature_store(float J, float n, float xhi, const float *mu,
                                                   const float *isd, uint16_t *x16)
 {
-    const float f[3] = {J, kappa, S};
+    const float f[3] = {J, n, xhi};
     uint16_t h[3];
-    for (int k = 0; k < 3; ++k) h[k] = art_bf16_rne((logf(fmaxf(f[k], 1e-30f)) - mu[k]) * isd[k]);
+    for (int k = 0; k < 3; ++k) h[k] = art_bf16_rne((art_feature_raw(k, f[k]) - mu[k]) * isd[k]);
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
     u4 *dst = reinterpret_cast<u4 *>(x16);
     dst[0] = u4{(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2], 0u, 0u};

@@ -33,7 +33,7 @@ constexpr int REAL_IN[NL] = {3, 32, 32, 32, 32, 32};   // channels that carry da
 constexpr int REAL_OUT[NL] = {32, 32, 32, 32, 32, 1};
 constexpr int RELU[NL] = {1, 1, 1, 1, 1, 0};
 constexpr long long MAX_CELLS = 11184810;              // 3 * 32 * 2 bytes per cell < 2 GiB
-constexpr char MAGIC[8] = {'A', 'R', 'T', 'S', 'G', 'C', 'K', '1'};
+constexpr char MAGIC[8] = {'A', 'R', 'T', 'S', 'G', 'C', 'K', '2'};   // features (log J, log n, x_HI)
 
 int wcount(int l) { return 27 * CIN[l] * 32; }
 
@@ -53,26 +53,11 @@ int sg_fail(int code, const std::string &msg) { return art_set_error(code, msg.c
         if (rc_ != ART_OK) return rc_;                                                           \
     } while (0)
 
-struct Stat3 {
-    float a[3];
-};
-
 // ---------------------------------------------------------------- kernels
 
-// Network input from the mesh's field records (bin 0 of nb) and J_coarse.
-__global__ __launch_bounds__(256) void features_rec_kernel(const float *__restrict__ J,
-                                                           const float2 *__restrict__ rec, int nb,
-                                                           float inv_h, long long V, Stat3 mu,
-                                                           Stat3 isd, uint16_t *__restrict__ x)
-{
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= V) return;
-    const float2 r = rec[v * nb];
-    art_feature_store(J[v], r.x * inv_h, r.y, mu.a, isd.a, x + v * 16);
-}
-
-// Outputs of an accepted prediction.
-__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ Js,
+// Outputs of an accepted prediction: J_in = J_in,coarse e^p, J = J_in + S.
+__global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ pred,
+                                                     const float *__restrict__ Jinc,
                                                      const float *__restrict__ Jc,
                                                      const float *__restrict__ Jexc,
                                                      const float2 *__restrict__ rec, int nb,
@@ -85,20 +70,21 @@ __global__ __launch_bounds__(256) void finish_kernel(const float *__restrict__ J
 {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const float j = Js[v], s = rec[v * nb].y;
+    const float jin = Jinc[v] * expf(pred[v]), s = rec[v * nb].y;
+    const float j = jin + s;
     if (J) J[v] = j;
-    if (J_in) J_in[v] = j - s;
-    if (Heat) Heat[v] = fmaf(h_in, j - s, h_src * s);
+    if (J_in) J_in[v] = jin;
+    if (Heat) Heat[v] = fmaf(h_in, jin, h_src * s);
     if (J_exact) J_exact[v] = j + (Jexc[v] - Jc[v]);
     if (Gamma) Gamma[v] = g0 * j;
 }
 
 // Per-block sums, sums of squares (double), minima and maxima of the three
-// log features; out[block][k][4].
+// raw features; out[block][k][4].
 constexpr int STAT_BLOCKS = 256;
 __global__ __launch_bounds__(256) void stats_kernel(const float *__restrict__ J,
-                                                    const float *__restrict__ kap,
-                                                    const float *__restrict__ S, long long V,
+                                                    const float *__restrict__ dens,
+                                                    const float *__restrict__ xhi, long long V,
                                                     double *__restrict__ out)
 {
     __shared__ double s1[3][256], s2[3][256];
@@ -107,9 +93,9 @@ __global__ __launch_bounds__(256) void stats_kernel(const float *__restrict__ J,
     double a1[3] = {0.0, 0.0, 0.0}, a2[3] = {0.0, 0.0, 0.0};
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (long long v = (long long)blockIdx.x * 256 + t; v < V; v += (long long)gridDim.x * 256) {
-        const float f[3] = {J[v], kap[v], S[v]};
+        const float f[3] = {J[v], dens[v], xhi[v]};
         for (int k = 0; k < 3; ++k) {
-            const float l = logf(fmaxf(f[k], 1e-30f));
+            const float l = art_feature_raw(k, f[k]);
             a1[k] += l;
             a2[k] += (double)l * l;
             lo[k] = fminf(lo[k], l);
@@ -282,7 +268,7 @@ struct art_surrogate {
              *x = nullptr;
     float *pred = nullptr, *partial = nullptr, *bpart = nullptr, *mpart = nullptr,
           *wpart = nullptr, *loss = nullptr;
-    float *Jc = nullptr, *Jexc = nullptr, *Js = nullptr, *Jf = nullptr;
+    float *Jc = nullptr, *Jexc = nullptr, *Jinc = nullptr, *Jf = nullptr, *Jinf = nullptr;
     unsigned *count = nullptr;
     double *spart = nullptr;
     std::vector<void *> mem;
@@ -385,7 +371,7 @@ int art_surrogate_create(int nx, int ny, int nz, unsigned long long seed, art_su
     for (int l = 0; l < NL - 1; ++l) A(&s->acts[l], V * 32);
     A(&s->dy[0], V * 32); A(&s->dy[1], V * 32);
     A(&s->g, V * 32); A(&s->gcf, V * 32); A(&s->xs, 3 * 32 * V); A(&s->x, V * 16);
-    A(&s->pred, V); A(&s->Jc, V); A(&s->Jexc, V); A(&s->Js, V); A(&s->Jf, V);
+    A(&s->pred, V); A(&s->Jc, V); A(&s->Jexc, V); A(&s->Jinc, V); A(&s->Jf, V); A(&s->Jinf, V);
     A(&s->partial, (size_t)s->nchunk * 27 * 32 * 32);
     A(&s->bpart, (size_t)s->nchunk_b * 32);
     A(&s->mpart, 256); A(&s->wpart, 257); A(&s->loss, 1); A(&s->count, 1);
@@ -462,20 +448,21 @@ int art_surrogate_get_stats(const art_surrogate *s, float *mu, float *sd, float 
 }
 
 int art_surrogate_fit_stats(art_surrogate *s, int n, const float *const *J_coarse,
-                            const float *const *kappa, const float *const *S, float margin,
+                            const float *const *density, const float *const *x_hi, float margin,
                             void *hip_stream)
 {
-    if (!s || n < 1 || !J_coarse || !kappa || !S || !(margin >= 0.0f))
+    if (!s || n < 1 || !J_coarse || !density || !x_hi || !(margin >= 0.0f))
         return sg_fail(ART_E_INVAL, "art_surrogate_fit_stats: bad arguments");
     for (int i = 0; i < n; ++i)
-        if (!J_coarse[i] || !kappa[i] || !S[i]) return sg_fail(ART_E_INVAL, "art_surrogate_fit_stats: NULL field");
+        if (!J_coarse[i] || !density[i] || !x_hi[i])
+            return sg_fail(ART_E_INVAL, "art_surrogate_fit_stats: NULL field");
     hipStream_t st = (hipStream_t)hip_stream;
     double sum[3] = {0, 0, 0}, sq[3] = {0, 0, 0};
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     std::vector<double> h((size_t)STAT_BLOCKS * 12);
     for (int i = 0; i < n; ++i) {
-        hipLaunchKernelGGL(stats_kernel, dim3(STAT_BLOCKS), dim3(256), 0, st, J_coarse[i], kappa[i], S[i],
-                           s->V, s->spart);
+        hipLaunchKernelGGL(stats_kernel, dim3(STAT_BLOCKS), dim3(256), 0, st, J_coarse[i], density[i],
+                           x_hi[i], s->V, s->spart);
         RCCHK(launch_status("art_surrogate_fit_stats"));
         SGCHK(hipMemcpyAsync(h.data(), s->spart, h.size() * 8, hipMemcpyDeviceToHost, st));
         SGCHK(hipStreamSynchronize(st));
@@ -506,12 +493,13 @@ int art_surrogate_fit_stats(art_surrogate *s, int n, const float *const *J_coars
     return ART_OK;
 }
 
-int art_surrogate_features(const art_surrogate *s, const float *J_coarse, const float *kappa,
-                           const float *S, void *x, void *hip_stream)
+int art_surrogate_features(const art_surrogate *s, const float *J_coarse, const float *density,
+                           const float *x_hi, void *x, void *hip_stream)
 {
-    if (!s || !J_coarse || !kappa || !S || !x) return sg_fail(ART_E_INVAL, "art_surrogate_features: NULL argument");
+    if (!s || !J_coarse || !density || !x_hi || !x)
+        return sg_fail(ART_E_INVAL, "art_surrogate_features: NULL argument");
     const float isd[3] = {1.0f / s->sd[0], 1.0f / s->sd[1], 1.0f / s->sd[2]};
-    return art_nn_features(J_coarse, kappa, S, (int)s->V, s->mu, isd, x, hip_stream);
+    return art_nn_features(J_coarse, density, x_hi, (int)s->V, s->mu, isd, x, hip_stream);
 }
 
 int art_surrogate_make_pair(art_surrogate *s, art_mesh *mesh, int nside_coarse, int nside_fine,
@@ -526,11 +514,13 @@ int art_surrogate_make_pair(art_surrogate *s, art_mesh *mesh, int nside_coarse, 
     RCCHK(check_mesh(s, mesh, &rec, &nb, &h, "art_surrogate_make_pair"));
     art_outputs oc{}, of{};
     oc.J = J_coarse;
+    oc.J_in = s->Jinc;
     of.J = J_fine ? J_fine : s->Jf;
+    of.J_in = s->Jinf;
     RCCHK(art_sweep(mesh, nside_coarse, nullptr, 0.0f, &oc, hip_stream));
     RCCHK(art_sweep(mesh, nside_fine, nullptr, 0.0f, &of, hip_stream));
-    RCCHK(art_nn_log_ratio(of.J, J_coarse, (int)s->V, target, hip_stream));
-    if (weight) RCCHK(art_nn_sq_weights(J_coarse, (int)s->V, lambda, s->wpart, weight, hip_stream));
+    RCCHK(art_nn_log_ratio(s->Jinf, s->Jinc, (int)s->V, target, hip_stream));
+    if (weight) RCCHK(art_nn_sq_weights(s->Jinc, (int)s->V, lambda, s->wpart, weight, hip_stream));
     return ART_OK;
 }
 
@@ -676,11 +666,12 @@ int art_surrogate_load(art_surrogate *s, const char *path, void *hip_stream)
     return ART_OK;
 }
 
-int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int nside_fine,
-                        const float *gamma_w, float err_bound, const art_outputs *out,
-                        int *used_fallback, float *est_err, void *hip_stream)
+int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, const float *density, const float *x_hi,
+                        int nside_coarse, int nside_fine, const float *gamma_w, float err_bound,
+                        const art_outputs *out, int *used_fallback, float *est_err, void *hip_stream)
 {
-    if (!mesh || !s || !out) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: NULL argument");
+    if (!mesh || !s || !out || !density || !x_hi)
+        return sg_fail(ART_E_INVAL, "art_sweep_surrogate: NULL argument");
     if (out->exit_sum) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: exit sums are not produced");
     if (gamma_w && !std::isfinite(gamma_w[0])) return sg_fail(ART_E_INVAL, "art_sweep_surrogate: gamma_w not finite");
     const float2 *rec;
@@ -691,19 +682,12 @@ int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int 
     const long long V = s->V;
     art_outputs oc{};
     oc.J = s->Jc;
+    oc.J_in = s->Jinc;
     oc.J_exact = s->Jexc;
     RCCHK(art_sweep(mesh, nside_coarse, gamma_w, 0.0f, &oc, hip_stream));
-    Stat3 mu, isd;
-    for (int k = 0; k < 3; ++k) {
-        mu.a[k] = s->mu[k];
-        isd.a[k] = 1.0f / s->sd[k];
-    }
-    hipLaunchKernelGGL(features_rec_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, s->Jc, rec, nb,
-                       (float)(1.0 / h), V, mu, isd, s->x);
-    RCCHK(launch_status("art_sweep_surrogate (features)"));
+    RCCHK(art_surrogate_features(s, s->Jc, density, x_hi, s->x, hip_stream));
     RCCHK(art_nn_ood_count(s->x, (int)V, s->lo, s->hi, s->count, hip_stream));
     RCCHK(forward(s, s->x, st));
-    RCCHK(art_nn_expand(s->Jc, s->pred, (int)V, s->Js, hip_stream));
     unsigned nout = 0;
     SGCHK(hipMemcpyAsync(&nout, s->count, 4, hipMemcpyDeviceToHost, st));
     SGCHK(hipStreamSynchronize(st));
@@ -714,9 +698,9 @@ int art_sweep_surrogate(art_mesh *mesh, art_surrogate *s, int nside_coarse, int 
     if (!accept) return art_sweep(mesh, nside_fine, gamma_w, 0.0f, out, hip_stream);
     float hw[8];
     art_mesh_heating(mesh, hw);
-    hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, s->Js, s->Jc, s->Jexc,
-                       rec, nb, gamma_w ? gamma_w[0] : 1.0f, hw[0], hw[4], V, out->J, out->J_in,
-                       out->J_exact, out->Gamma, out->Heat);
+    hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(V, 256)), dim3(256), 0, st, s->pred, s->Jinc, s->Jc,
+                       s->Jexc, rec, nb, gamma_w ? gamma_w[0] : 1.0f, hw[0], hw[4], V, out->J,
+                       out->J_in, out->J_exact, out->Gamma, out->Heat);
     return launch_status("art_sweep_surrogate (outputs)");
 }
 

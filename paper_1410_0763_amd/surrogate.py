@@ -2,8 +2,9 @@
 argument marshalling only.
 
 The surrogate is a 3-D convolution network (6 layers, 3^3 taps, 32 channels,
-about 1.1e5 parameters) that maps a coarse sweep's log J plus log kappa and
-log S to log(J_fine / J_coarse).  Its parameters, optimiser state, work
+about 1.1e5 parameters) that maps a coarse sweep's log J plus the log density
+and the neutral fraction to log(J_in,fine / J_in,coarse), J_in being the
+incoming part of J = J_in + S.  Its parameters, optimiser state, work
 buffers, training step, inference, acceptance gate with fallback to the fine
 sweep, and checkpoints all live in the HIP library; torch tensors serve as
 device buffers and torch streams as HIP streams.  The surrogate is not part of
@@ -71,15 +72,15 @@ class Surrogate:
         st = self.stats
         self.set_stats(st["mu"], st["sd"], st["lo"], st["hi"], val_err)
 
-    def fit_stats(self, J_coarse, kappa, S, margin: float = 1.0, stream=None):
+    def fit_stats(self, J_coarse, density, x_hi, margin: float = 1.0, stream=None):
         """Statistics from lists of device float32 [V] tensors (synchronises)."""
         n = len(J_coarse)
-        arrs = [(ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) for ts in (J_coarse, kappa, S)]
+        arrs = [(ctypes.c_void_p * n)(*[t.data_ptr() for t in ts]) for ts in (J_coarse, density, x_hi)]
         _check(load().art_surrogate_fit_stats(self._h, n, *arrs, float(margin),
                                               _stream_ptr(stream)))
 
-    def features(self, J, kappa, S, x, stream=None):
-        _check(load().art_surrogate_features(self._h, _ptr(J), _ptr(kappa), _ptr(S), _ptr(x),
+    def features(self, J, density, x_hi, x, stream=None):
+        _check(load().art_surrogate_features(self._h, _ptr(J), _ptr(density), _ptr(x_hi), _ptr(x),
                                              _stream_ptr(stream)))
 
     # -- training and inference -------------------------------------------
@@ -125,8 +126,8 @@ def _check_count(rc):
 
 def make_pair(mesh, model, nside_coarse, nside_fine, target, weight=None, J_coarse=None,
               J_fine=None, lam=1.0, stream=None):
-    """Training pair of the field loaded in mesh: target = log(J_fine /
-    J_coarse) and the loss weights (art_surrogate_make_pair).  Returns
+    """Training pair of the field loaded in mesh: target = log(J_in,fine /
+    J_in,coarse) and the loss weights (art_surrogate_make_pair).  Returns
     (J_coarse, J_fine) device tensors [V]."""
     import torch
     V = model.V
@@ -138,9 +139,11 @@ def make_pair(mesh, model, nside_coarse, nside_fine, target, weight=None, J_coar
     return Jc, Jf
 
 
-def sweep_surrogate(mesh, model, nside_coarse=2, nside_fine=16, err_bound=0.05, gamma_w=None,
-                    out=None, stream=None):
-    """art_sweep_surrogate: returns (outputs dict, used_fallback, est_err)."""
+def sweep_surrogate(mesh, model, density, x_hi, nside_coarse=2, nside_fine=16, err_bound=0.05,
+                    gamma_w=None, out=None, stream=None):
+    """art_sweep_surrogate for the field in mesh made from density and x_hi
+    (device float32 tensors of the mesh's cells): returns (outputs dict,
+    used_fallback, est_err)."""
     if out is None:
         out = mesh.alloc_outputs(nside_fine)
     o = Outputs.of({k: v for k, v in out.items() if k != "exit_sum"})
@@ -150,7 +153,8 @@ def sweep_surrogate(mesh, model, nside_coarse=2, nside_fine=16, err_bound=0.05, 
         gw = ctypes.cast(arr, ctypes.c_void_p)
     fb = ctypes.c_int()
     est = ctypes.c_float()
-    _check(load().art_sweep_surrogate(mesh._h, model._h, nside_coarse, nside_fine, gw,
+    _check(load().art_sweep_surrogate(mesh._h, model._h, _ptr(density.contiguous()),
+                                      _ptr(x_hi.contiguous()), nside_coarse, nside_fine, gw,
                                       float(err_bound), ctypes.byref(o), ctypes.byref(fb),
                                       ctypes.byref(est), _stream_ptr(stream)))
     return out, bool(fb.value), float(est.value)

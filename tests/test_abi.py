@@ -88,7 +88,7 @@ def test_surrogate_argument_checks_without_gpu():
     assert L.art_surrogate_create(320, 320, 320, 0, ctypes.byref(h)) == -5     # above the 2 GiB buffers
     assert L.art_surrogate_n_params(None) == -1
     assert L.art_surrogate_destroy(None) == 0
-    assert L.art_sweep_surrogate(None, None, 2, 16, None, 1.0, None, None, None, None) == -1
+    assert L.art_sweep_surrogate(None, None, None, None, 2, 16, None, 1.0, None, None, None, None) == -1
     assert L.art_sha256(None, 5, ctypes.create_string_buffer(32)) == -1
 
 

@@ -362,29 +362,36 @@ def test_gate_and_argument_errors():
     s = torch.from_numpy(rng.uniform(0.0, 1.0, (1,) + shape).astype(np.float32)).cuda()
     mesh = art.Mesh(32, 8, 8)
     mesh.set_fields(k, s)
+    n = torch.from_numpy(rng.lognormal(0.0, 1.0, 8 * 8 * 32).astype(np.float32)).cuda()
+    xh = torch.from_numpy(rng.uniform(0.0, 1.0, 8 * 8 * 32).astype(np.float32)).cuda()
     model = SG.Surrogate(shape, seed=0)
-    out, fb, est = SG.sweep_surrogate(mesh, model, 1, 2, err_bound=1e9)
+    out, fb, est = SG.sweep_surrogate(mesh, model, n, xh, 1, 2, err_bound=1e9)
     assert fb and np.isnan(est)
     ref = mesh.sweep(2)
     torch.cuda.synchronize()
     for key in ("J", "J_in", "J_exact", "Gamma"):
         assert torch.equal(out[key], ref[key]), key
     model.set_val_err(0.0)
-    out, fb, est = SG.sweep_surrogate(mesh, model, 1, 2, err_bound=1e9)
+    out, fb, est = SG.sweep_surrogate(mesh, model, n, xh, 1, 2, err_bound=1e9)
     assert not fb and est == 0.0
     o = mesh.alloc_outputs(2, exit_sum=True)
     outs = art.Outputs.of(o)
-    rc = art.load().art_sweep_surrogate(mesh._h, model._h, 1, 2, None, 1e9, outs, None, None,
-                                        art._stream_ptr(None))
-    assert rc == -1 and b"exit" in art.load().art_last_error()
+    L = art.load()
+    rc = L.art_sweep_surrogate(mesh._h, model._h, art._ptr(n), art._ptr(xh), 1, 2, None, 1e9, outs,
+                               None, None, art._stream_ptr(None))
+    assert rc == -1 and b"exit" in L.art_last_error()
+    outs = art.Outputs.of(mesh.alloc_outputs(2))
+    rc = L.art_sweep_surrogate(mesh._h, model._h, None, art._ptr(xh), 1, 2, None, 1e9, outs,
+                               None, None, art._stream_ptr(None))
+    assert rc == -1, "a missing density is rejected"
     other = art.Mesh(32, 8, 4)
     other.set_fields(k[:, :4].contiguous(), s[:, :4].contiguous())
     with pytest.raises(art.ArtError, match="shape"):
-        SG.sweep_surrogate(other, model, 1, 2)
+        SG.sweep_surrogate(other, model, n, xh, 1, 2)
     two = art.Mesh(32, 8, 8)
     two.set_fields(torch.cat([k, k]), torch.cat([s, s]))
     with pytest.raises(art.ArtError, match="one bin"):
-        SG.sweep_surrogate(two, model, 1, 2)
+        SG.sweep_surrogate(two, model, n, xh, 1, 2)
     for m in (mesh, other, two):
         m.close()
 
@@ -398,13 +405,17 @@ def test_fit_stats_matches_numpy():
     shape = (8, 16, 32)
     V = 8 * 16 * 32
     rng = np.random.default_rng(12)
-    fields = [[rng.lognormal(0.0, 1.5, V).astype(np.float32) for _ in range(3)] for _ in range(3)]
-    fields[1][1][:7] = 0.0                      # vacuum cells: log floored at 1e-30
+    # per field: J_coarse (lognormal), density (lognormal), neutral fraction (uniform)
+    fields = [[rng.lognormal(0.0, 1.5, V).astype(np.float32), rng.lognormal(0.0, 1.0, V).astype(np.float32),
+               rng.uniform(0.0, 1.0, V).astype(np.float32)] for _ in range(3)]
+    fields[1][1][:7] = 0.0                      # empty cells: log floored at 1e-30
+
+    def raw(c, a):                               # log for J and n, the value for x_HI
+        return np.log(np.maximum(a.astype(np.float64), 1e-30)) if c < 2 else a.astype(np.float64)
     model = SG.Surrogate(shape, seed=0)
     model.fit_stats(*[[_dev(f[c]) for f in fields] for c in range(3)], margin=0.5)
     st = model.stats
-    logs = np.stack([np.concatenate([np.log(np.maximum(f[c].astype(np.float64), 1e-30)) for f in fields])
-                     for c in range(3)])
+    logs = np.stack([np.concatenate([raw(c, f[c]) for f in fields]) for c in range(3)])
     mu, sd = logs.mean(1), logs.std(1)
     z = (logs - mu[:, None]) / sd[:, None]
     np.testing.assert_allclose(st["mu"], mu, rtol=1e-5, atol=1e-5)
@@ -416,14 +427,14 @@ def test_fit_stats_matches_numpy():
     x = torch.zeros((V, 16), dtype=torch.int16, device="cuda")
     model.features(*[_dev(fields[0][c]) for c in range(3)], x)
     torch.cuda.synchronize()
-    ref = np.stack([(np.log(np.maximum(fields[0][c], 1e-30)).astype(np.float32) - np.float32(st["mu"][c]))
+    ref = np.stack([(raw(c, fields[0][c]).astype(np.float32) - np.float32(st["mu"][c]))
                     * np.float32(1.0 / np.float32(st["sd"][c])) for c in range(3)], 1).astype(np.float32)
     got = bf16_value(x.cpu().numpy()[:, :3])
     assert np.max(np.abs(got - bf16_value(bf16_bits(ref)))) <= 2.0 ** -7 * np.max(np.abs(ref))
     assert not x.cpu().numpy()[:, 3:].any()
 
 
-def _pairs(model, mesh, idx, train):
+def _pairs(model, mesh, idx, train, lam):
     import torch
     from paper_1410_0763_amd import media
     from paper_1410_0763_amd import surrogate as SG
@@ -435,19 +446,27 @@ def _pairs(model, mesh, idx, train):
         mesh.set_fields(k, s)
         t = torch.zeros(model.V, dtype=torch.float32, device="cuda")
         w = torch.zeros(model.V, dtype=torch.float32, device="cuda")
-        Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w)
-        out.append(dict(m=m, k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf))
+        Jc, Jf = SG.make_pair(mesh, model, 2, 16, t, w, lam=lam)
+        out.append(dict(m=m, k=k, s=s, t=t, w=w, Jc=Jc, Jf=Jf,
+                        n=torch.from_numpy(m.density).cuda().reshape(-1),
+                        x=torch.from_numpy(m.x_hi).cuda().reshape(-1)))
     return out
+
+
+# training recipe of the gain test (the benchmark trains the same way on more fields)
+GAIN_TRAIN_FIELDS, GAIN_STEPS, GAIN_LAMBDA = 32, 2400, 1.0
+GAIN_MARGIN = 0.05          # held-out relative L2 of J at least 5% below the coarse sweep's
 
 
 def test_surrogate_gain_and_fallback():
     """128^3 fields: trained on coarse (Nside 2) -> fine (Nside 16) pairs, the
-    surrogate is closer to the fine sweep than the coarse sweep on held-out
-    fields (per-cell RMS of log(J / J_fine) at least 25% lower, relative L2 of
-    J within 25% of the coarse one: the loss weights cells by
-    (J^2 / mean J^2 + 1) / 2), coarse sweep + inference is faster than the
-    fine sweep, and the gate falls back to the fine sweep when the bound is 0
-    or the field is out of distribution."""
+    surrogate beats the coarse sweep on held-out fields in the gate's own
+    metric (relative L2 error of J against the fine sweep, at least
+    GAIN_MARGIN lower) and in the per-cell RMS of log(J / J_fine); its
+    accepted outputs equal the same steps through the other entry points;
+    coarse sweep + inference is faster than the fine sweep; and the gate falls
+    back to the fine sweep when the bound is 0 or the inputs are out of
+    distribution."""
     _case("surrogate gain and fallback, 128^3, Nside 2 -> 16")
     import time
     import torch
@@ -456,28 +475,27 @@ def test_surrogate_gain_and_fallback():
     shape = (128, 128, 128)
     model = SG.Surrogate(shape, seed=0)
     mesh = art.Mesh(*shape[::-1])
-    train = _pairs(model, mesh, range(16), True)
+    train = _pairs(model, mesh, range(GAIN_TRAIN_FIELDS), True, GAIN_LAMBDA)
     # feature statistics from the first fields, then the network inputs
-    model.fit_stats([p["Jc"] for p in train[:2]], [p["k"].reshape(-1) for p in train[:2]],
-                    [p["s"].reshape(-1) for p in train[:2]], margin=1.0)
+    model.fit_stats([p["Jc"] for p in train[:4]], [p["n"] for p in train[:4]],
+                    [p["x"] for p in train[:4]], margin=1.0)
     for p in train:
-        p["x"] = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
-        model.features(p["Jc"], p["k"].reshape(-1), p["s"].reshape(-1), p["x"])
-    test = _pairs(model, mesh, range(3), False)
-    steps = 800
+        p["X"] = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
+        model.features(p["Jc"], p["n"], p["x"], p["X"])
+    test = _pairs(model, mesh, range(4), False, GAIN_LAMBDA)
     t0 = time.perf_counter()
-    for it in range(steps):
-        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / steps)) + 1e-5
+    for it in range(GAIN_STEPS):
+        lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / GAIN_STEPS)) + 1e-5
         p = train[it % len(train)]
-        loss = model.train_step(p["x"], p["t"], lr=lr, weight=p["w"])
+        loss = model.train_step(p["X"], p["t"], lr=lr, weight=p["w"])
     torch.cuda.synchronize()
-    print(f"trained {steps} steps in {time.perf_counter() - t0:.1f} s, last loss {loss.item():.4e}",
-          flush=True)
+    print(f"trained {GAIN_STEPS} steps on {GAIN_TRAIN_FIELDS} fields in {time.perf_counter() - t0:.1f} s, "
+          f"last loss {loss.item():.4e}", flush=True)
     err_c, err_s, lr_c, lr_s = [], [], [], []
     model.set_val_err(0.0)
     for p in test:
         mesh.set_fields(p["k"], p["s"])
-        out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1e9)
+        out, fb, est = SG.sweep_surrogate(mesh, model, p["n"], p["x"], 2, 16, err_bound=1e9)
         assert not fb
         J = out["J"].reshape(-1)
         Jf = p["Jf"]
@@ -489,35 +507,36 @@ def test_surrogate_gain_and_fallback():
           flush=True)
     print(f"held-out relative L2 error:      coarse {np.mean(err_c):.4f}  surrogate {np.mean(err_s):.4f}",
           flush=True)
-    assert np.mean(lr_s) < 0.75 * np.mean(lr_c)
-    assert np.mean(err_s) < 1.25 * np.mean(err_c)
+    assert np.mean(err_s) < (1.0 - GAIN_MARGIN) * np.mean(err_c)
+    assert np.mean(lr_s) < np.mean(lr_c)
+    # the gate's error estimate is the metric asserted above
     model.set_val_err(float(np.mean(err_s)))
     # the accepted outputs against the same steps through the other entry points
     p = test[0]
     mesh.set_fields(p["k"], p["s"])
     mesh.set_heating([0.3], [0.1])
-    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0, gamma_w=[0.5])
-    assert not fb
+    out, fb, est = SG.sweep_surrogate(mesh, model, p["n"], p["x"], 2, 16, err_bound=1.0, gamma_w=[0.5])
+    assert not fb and abs(est - np.mean(err_s)) < 1e-6
     c = mesh.sweep(2)
     x = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
-    model.features(c["J"].reshape(-1), p["k"].reshape(-1), p["s"].reshape(-1), x)
-    Jm = c["J"].reshape(-1) * torch.exp(model.forward(x))
+    model.features(c["J"].reshape(-1), p["n"], p["x"], x)
+    Jin_m = c["J_in"].reshape(-1) * torch.exp(model.forward(x))
     torch.cuda.synchronize()
+    S = p["s"].reshape(-1)
     Js = out["J"].reshape(-1)
-    assert torch.allclose(Js, Jm, rtol=2e-6, atol=0)
-    assert torch.allclose(out["J_in"].reshape(-1), Js - p["s"].reshape(-1), rtol=0, atol=1e-6 * Js.max().item())
+    assert torch.allclose(out["J_in"].reshape(-1), Jin_m, rtol=2e-6, atol=0)
+    assert torch.allclose(Js, Jin_m + S, rtol=2e-6, atol=0)
     assert torch.allclose(out["Gamma"].reshape(-1), 0.5 * Js, rtol=1e-6, atol=0)
-    Jin = Js - p["s"].reshape(-1)
-    assert torch.allclose(out["Heat"].reshape(-1), 0.3 * Jin + 0.1 * p["s"].reshape(-1), rtol=1e-5,
+    assert torch.allclose(out["Heat"].reshape(-1), 0.3 * Jin_m + 0.1 * S, rtol=1e-5,
                           atol=1e-6 * Js.max().item())
     assert torch.allclose(out["J_exact"].reshape(-1), Js + (c["J_exact"] - c["J"]).reshape(-1),
                           rtol=0, atol=1e-6 * Js.max().item())
     # time: coarse sweep + inference against the fine sweep
-    SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0)
+    SG.sweep_surrogate(mesh, model, p["n"], p["x"], 2, 16, err_bound=1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(3):
-        SG.sweep_surrogate(mesh, model, 2, 16, err_bound=1.0)
+        SG.sweep_surrogate(mesh, model, p["n"], p["x"], 2, 16, err_bound=1.0)
     torch.cuda.synchronize()
     t_sur = (time.perf_counter() - t0) / 3
     mesh.sweep(16)
@@ -529,12 +548,11 @@ def test_surrogate_gain_and_fallback():
     t_fine = (time.perf_counter() - t0) / 3
     print(f"coarse + inference {1e3 * t_sur:.1f} ms, fine sweep {1e3 * t_fine:.1f} ms", flush=True)
     assert t_sur < t_fine
-    # forced fallbacks: bound 0, and an out-of-distribution (vacuum) field
-    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=0.0)
+    # forced fallbacks: bound 0, and inputs out of distribution (densities
+    # a million times those seen in training)
+    out, fb, est = SG.sweep_surrogate(mesh, model, p["n"], p["x"], 2, 16, err_bound=0.0)
     assert fb and torch.allclose(out["J"].reshape(-1), p["Jf"], rtol=1e-6, atol=0)
-    vac_k = torch.zeros_like(p["k"])
-    mesh.set_fields(vac_k, p["s"])
-    out, fb, est = SG.sweep_surrogate(mesh, model, 2, 16, err_bound=0.5)
-    print(f"vacuum field: used_fallback {fb}, estimated error {est:.3f}", flush=True)
-    assert fb
+    out, fb, est = SG.sweep_surrogate(mesh, model, p["n"] * 1e6, p["x"], 2, 16, err_bound=0.5)
+    print(f"out-of-distribution densities: used_fallback {fb}, estimated error {est:.3f}", flush=True)
+    assert fb and torch.allclose(out["J"].reshape(-1), p["Jf"], rtol=1e-6, atol=0)
     mesh.close()
