@@ -431,6 +431,70 @@ def bench_point(steps=5, cpu=True):
     print(json.dumps(rec), flush=True)
 
 
+def bench_chem(steps=5, cpu=True):
+    """Chemistry and energy update (Appendices B-D) of every cell of a 128^3
+    medium, driven by the rates of its own Nside 2 sweep: HIP events around
+    art_chem_step, the FP64 oracle timed on a sample of cells beside it."""
+    import numpy as np
+    import torch
+    from paper_1410_0763_amd import art, media
+    m = media.clumpy_medium((128, 128, 128), nside=2, sigma_ln=1.5, seed=5100, spheres=16, name="chem128")
+    nb, nz, ny, nx = m.kappa.shape
+    n = nx * ny * nz
+    mesh = art.Mesh(nx, ny, nz)
+    mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+    mesh.set_heating([1.5], [0.1])
+    out = mesh.sweep(m.nside)
+    G = out["Gamma"].reshape(-1).contiguous()
+    H = out["Heat"].reshape(-1).contiguous()
+    lt = np.linspace(1.0, 9.0, 81)
+    T = 10.0 ** lt
+    tabs = dict(alpha=2.0 * (T / 1e4) ** -0.7, k_ci=0.5 * np.exp(-1.6e5 / T),
+                cool_I=3e-2 * np.exp(-1.2e5 / T), cool_II=1e-4 * (T / 1e4) ** 0.5)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    tables = {k: d(v) for k, v in tabs.items()}
+    nH = d(m.density.reshape(-1))
+    x0, u0 = m.x_hi.reshape(-1).astype(np.float64), np.full(n, 300.0)
+    xg, ug = d(x0), d(u0)
+    ns = torch.empty(n, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(steps + 1):
+        xg.copy_(d(x0))
+        ug.copy_(d(u0))
+        torch.cuda.synchronize()
+        e0.record()
+        art.chem_step(nH, nH, G, H, xg, ug, 0.5, tables, 1.0, 0.1, T_per_u=10.0, nsub=ns)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = min(times[1:])
+    subs = int(ns.to(torch.int64).sum().item())
+    rec = {"metric": "cells/s of the chemistry and energy update (Appendices B-D, hydrogen network)",
+           "value": n / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": steps, "ms_per_step": ms,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "substeps": subs, "substep_cells_per_s": subs / (ms / 1e3),
+           "config": {"workload": "128^3 lognormal (sigma_ln 1.5) + 16 spheres, rates of its Nside 2 "
+                                  "sweep, one radiative step dt = 0.5, 81-point synthetic rate tables"},
+           "roofline": None}
+    if cpu:
+        from oracle import chem as C
+        p = C.default_params(nT=81, logT_min=1.0, logT_max=9.0, **tabs)
+        p.update(T_per_u=10.0)
+        idx = np.random.default_rng(1).integers(0, n, 400)
+        Gc = G.cpu().numpy().astype(np.float64)
+        Hc = H.cpu().numpy().astype(np.float64)
+        nHc = m.density.reshape(-1).astype(np.float64)
+        t0 = time.perf_counter()
+        C.step(nHc[idx], nHc[idx], Gc[idx], Hc[idx], x0[idx], u0[idx], 0.5, p)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": len(idx) / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{len(idx)} random cells of the same step in {dt:.1f} s "
+                                         "(plain Python loops)"}
+    mesh.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +513,8 @@ def main():
                     help="measure the learned surrogate (128^3) instead of the 256^3 sweep")
     ap.add_argument("--point", action="store_true",
                     help="measure point-source RT (128^3, 16 sources) instead of the 256^3 sweep")
+    ap.add_argument("--chem", action="store_true",
+                    help="measure the chemistry and energy update (128^3) instead of the 256^3 sweep")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(*args.traffic_from, sweeps=args.sweeps)
@@ -473,6 +539,9 @@ def main():
         return
     if args.point:
         bench_point(steps=args.steps, cpu=not args.no_cpu_baseline)
+        return
+    if args.chem:
+        bench_chem(steps=args.steps, cpu=not args.no_cpu_baseline)
         return
     m = media.plain_256()
     nb, nz, ny, nx = m.kappa.shape

@@ -1,0 +1,76 @@
+/*
+ * art_chem.h -- the chemistry and energy update that follows a radiative-
+ * transfer step (Tanaka et al., arXiv:1410.0763, Appendix B ionisation
+ * balance, Appendix C photo-heating and radiative cooling, Appendix D
+ * iteration and timestep control), for a hydrogen network (HI, HII, e).
+ *
+ * The paper cites its rate fits without printing them, so the caller supplies
+ * the rate coefficients as tables on a uniform grid of log10 T; they are
+ * interpolated linearly in log10 T and held at the end values outside the
+ * grid.  Per cell, with n_e = n_HII = n_H - n_HI and T = T_per_u u / (1 + x_e),
+ * x_e = n_HII / n_H:
+ *
+ *   dn_HI/dt = alpha(T) n_e n_HII - (k_ci(T) n_e + Gamma) n_HI
+ *   du/dt    = (Heat n_HI - n_e (cool_I(T) n_HI + cool_II(T) n_HII)) / rho
+ *
+ * Gamma and Heat are the photo-ionisation and photo-heating rates per HI atom
+ * from the transfer (art_sweep's Gamma and Heat, art_point_sources, or their
+ * sum), constant over the step because the transfer equation is static.  The
+ * step dt is divided into sub-steps h = min(dt_chem, rest of dt), dt_chem =
+ * eps_e |n_e / (dn_e/dt)| + eps_HI |n_HI / (dn_HI/dt)| (a term whose rate is 0
+ * is infinite; after max_sub sub-steps the rest is taken at once).  In a
+ * sub-step the backward-difference update n_HI' = (C h + n_HI) / (1 + D h),
+ * C = alpha n_e' n_HII', D = k_ci n_e' + Gamma at the advanced time, is solved
+ * exactly for n_HI' (with hydrogen alone it is a quadratic at fixed T), then
+ * u' = u + h (Heat n_HI' - Lambda(n', u')) / rho is solved for u' by 64
+ * bisection halvings on [u_floor, max(u_floor, u + h Heat n_HI' / rho)],
+ * u_floor = 10^logT_min / T_per_u; the two are iterated at most max_iter times
+ * until |n_e^(i) - n_e^(i-1)| <= eps n_e^(i) and |u^(i) - u^(i-1)| <= eps
+ * u^(i).  All arithmetic is double precision.
+ *
+ * Conventions as in art.h: ART_OK or a negative ART_E_* code, art_last_error
+ * on failure, work queued on hip_stream, device pointers owned by the caller.
+ */
+#ifndef ART_CHEM_H
+#define ART_CHEM_H
+
+#include "art.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int nT;                 /* table points, >= 2 */
+    double logT_min;        /* log10 T of the first point */
+    double dlogT;           /* spacing in log10 T, > 0 */
+    const double *alpha;    /* device [nT]: radiative recombination of HII, per n_e n_HII */
+    const double *k_ci;     /* device [nT]: collisional ionisation of HI, per n_e n_HI */
+    const double *cool_I;   /* device [nT]: cooling per n_e n_HI (collisional ionisation and excitation) */
+    const double *cool_II;  /* device [nT]: cooling per n_e n_HII (recombination, bremsstrahlung) */
+    double T_per_u;         /* T = T_per_u u / (1 + x_e), > 0 */
+    double eps;             /* convergence tolerance of the iteration (the paper: 1e-3), > 0 */
+    double eps_e, eps_HI;   /* timestep factors (the paper: 0.2 and 0.002), >= 0, not both 0 */
+    int max_iter;           /* iterations per sub-step, >= 1 */
+    int max_sub;            /* sub-steps before the rest of dt is taken at once, >= 0 */
+} art_chem_params;
+
+/*
+ * Advance ncell cells by dt (finite, >= 0).  n_H, rho: device double [ncell],
+ * hydrogen number density and mass density (cells with n_H <= 0 are left as
+ * they are, with dt_chem = +inf and nsub = 0); Gamma, Heat: device float
+ * [ncell], per HI atom; x_HI (in [0, 1]) and u (>= 0): device double [ncell],
+ * updated in place; dt_chem: device double [ncell] or NULL, the chemical
+ * timestep at the final state (the radiative step of Appendix D is F times
+ * its minimum); nsub: device int [ncell] or NULL, sub-steps taken.
+ * ART_E_INVAL for a bad size, pointer or parameter, before any GPU work.
+ */
+int art_chem_step(long long ncell, const double *n_H, const double *rho, const float *Gamma,
+                  const float *Heat, double *x_HI, double *u, double dt, const art_chem_params *p,
+                  double *dt_chem, int *nsub, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ART_CHEM_H */

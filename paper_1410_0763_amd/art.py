@@ -37,6 +37,8 @@ SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_
               "art_surrogate_save", "art_surrogate_load", "art_sweep_surrogate", "art_sha256")
 # include/art_point.h: rates from point sources
 PT_EXPORTS = ("art_point_sources", "art_point_sources_noalloc")
+# include/art_chem.h: chemistry and energy update of a radiative step
+CHEM_EXPORTS = ("art_chem_step",)
 
 
 class ArtError(RuntimeError):
@@ -54,6 +56,15 @@ class Outputs(ctypes.Structure):
     @classmethod
     def of(cls, out: dict):
         return cls(*(_ptr(out.get(k)) for k in OUTPUT_KEYS))
+
+
+class ChemParams(ctypes.Structure):
+    """art_chem_params (include/art_chem.h); the tables are device pointers."""
+    _fields_ = [("nT", ctypes.c_int), ("logT_min", ctypes.c_double), ("dlogT", ctypes.c_double),
+                ("alpha", ctypes.c_void_p), ("k_ci", ctypes.c_void_p), ("cool_I", ctypes.c_void_p),
+                ("cool_II", ctypes.c_void_p), ("T_per_u", ctypes.c_double), ("eps", ctypes.c_double),
+                ("eps_e", ctypes.c_double), ("eps_HI", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("max_sub", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -134,7 +145,9 @@ def load(path: str = LIB_PATH):
     L.art_sha256.argtypes = [vp, ctypes.c_ulonglong, vp]
     L.art_point_sources.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
     L.art_point_sources_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
-    for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS:
+    L.art_chem_step.argtypes = [ctypes.c_longlong, vp, vp, vp, vp, vp, vp, d,
+                                ctypes.POINTER(ChemParams), vp, vp, vp]
+    for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS + CHEM_EXPORTS:
         if name != "art_last_error":
             getattr(L, name).restype = i
     _lib = L
@@ -344,6 +357,21 @@ class Mesh:
         _check(load().art_sweep_range(self._h, nside, d_begin, d_end, float(I_bc), _ptr(A1),
                                       _ptr(A2), _stream_ptr(stream)))
         return A1, A2
+
+
+def chem_step(n_H, rho, Gamma, Heat, x_HI, u, dt, tables, logT_min, dlogT, T_per_u=1.0, eps=1e-3,
+              eps_e=0.2, eps_HI=0.002, max_iter=100, max_sub=100000, dt_chem=None, nsub=None,
+              stream=None):
+    """art_chem_step on device tensors (n_H, rho, x_HI, u float64; Gamma,
+    Heat float32; x_HI and u updated in place).  tables: dict of float64
+    device tensors alpha, k_ci, cool_I, cool_II on the log10 T grid."""
+    nT = int(tables["alpha"].numel())
+    prm = ChemParams(nT, float(logT_min), float(dlogT), *[_ptr(tables[k]) for k in
+                     ("alpha", "k_ci", "cool_I", "cool_II")], float(T_per_u), float(eps),
+                     float(eps_e), float(eps_HI), int(max_iter), int(max_sub))
+    _check(load().art_chem_step(int(n_H.numel()), _ptr(n_H), _ptr(rho), _ptr(Gamma), _ptr(Heat),
+                                _ptr(x_HI), _ptr(u), float(dt), ctypes.byref(prm), _ptr(dt_chem),
+                                _ptr(nsub), _stream_ptr(stream)))
 
 
 def tune_cache(op: str, path=None):

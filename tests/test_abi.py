@@ -36,12 +36,39 @@ def test_point_header_and_binding_agree():
     assert _declared("art_point.h") == sorted(art.PT_EXPORTS)
 
 
+def test_chem_header_and_binding_agree():
+    from paper_1410_0763_amd import art
+    assert _declared("art_chem.h") == sorted(art.CHEM_EXPORTS)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1410_0763_amd import art
     L = art.load()
     for name in (_declared() + _declared("art_nn.h") + _declared("art_surrogate.h") +
-                 _declared("art_point.h")):
+                 _declared("art_point.h") + _declared("art_chem.h")):
         assert hasattr(L, name), name
+
+
+def test_chem_argument_checks_without_gpu():
+    """Bad sizes, pointers and parameters are rejected before any launch."""
+    from paper_1410_0763_amd import art
+    L = art.load()
+    p = ctypes.c_void_p(1)
+    good = dict(nT=61, logT_min=1.0, dlogT=0.1, alpha=p, k_ci=p, cool_I=p, cool_II=p, T_per_u=1.0,
+                eps=1e-3, eps_e=0.2, eps_HI=0.002, max_iter=100, max_sub=1000)
+
+    def call(n=4, dt=1.0, nullcell=False, **kw):
+        prm = art.ChemParams(**dict(good, **kw))
+        cell = None if nullcell else p
+        return L.art_chem_step(n, cell, p, p, p, p, p, dt, ctypes.byref(prm), None, None, None)
+    assert call(n=0) == 0
+    assert call(n=-1) == -1
+    assert call(nullcell=True) == -1
+    assert call(dt=-1.0) == -1 and call(dt=float("inf")) == -1
+    assert call(nT=1) == -1 and call(dlogT=0.0) == -1 and call(alpha=None) == -1
+    assert call(T_per_u=0.0) == -1 and call(eps=0.0) == -1 and call(eps_e=0.0, eps_HI=0.0) == -1
+    assert call(max_iter=0) == -1 and call(max_sub=-1) == -1
+    assert L.art_chem_step(4, p, p, p, p, p, p, 1.0, None, None, None, None) == -1
 
 
 def test_point_argument_checks_without_gpu():
