@@ -513,6 +513,8 @@ def main():
                     help="measure the learned surrogate (128^3) instead of the 256^3 sweep")
     ap.add_argument("--point", action="store_true",
                     help="measure point-source RT (128^3, 16 sources) instead of the 256^3 sweep")
+    ap.add_argument("--sg-fields", type=int, default=64, help="training fields of --surrogate")
+    ap.add_argument("--sg-steps", type=int, default=4800, help="training steps of --surrogate")
     ap.add_argument("--chem", action="store_true",
                     help="measure the chemistry and energy update (128^3) instead of the 256^3 sweep")
     args = ap.parse_args()
@@ -535,7 +537,7 @@ def main():
         bench_batched()
         return
     if args.surrogate:
-        bench_surrogate()
+        bench_surrogate(train_fields=args.sg_fields, steps=args.sg_steps)
         return
     if args.point:
         bench_point(steps=args.steps, cpu=not args.no_cpu_baseline)

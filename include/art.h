@@ -195,6 +195,17 @@ int art_batch_launch(art_batch *batch, void *hip_stream);
 int art_batch_stats(art_batch *batch, long long *segment_bins, float *ms);
 int art_batch_destroy(art_batch *batch);
 
+/* The batched form under the names of its graph: art_sweep_batched creates
+ * the batch of n meshes (I_bc = 0, one wave per workgroup) as *graph and
+ * replays it once on hip_stream; art_graph_launch replays it again;
+ * art_graph_destroy releases it.  Same rules as art_batch_create. */
+typedef struct art_batch art_graph;
+int art_sweep_batched(art_mesh *const *meshes, const int *nside, int n,
+                      const float *const *gamma_w, const art_outputs *outs, art_graph **graph,
+                      void *hip_stream);
+int art_graph_launch(art_graph *graph, void *hip_stream);
+int art_graph_destroy(art_graph *graph);
+
 /* The block-wavefront schedule a sweep of an nx x ny x nz mesh with launch
  * shape t runs (host only, no device work; Sect. 3.1 and 3.3: single writers
  * without atomics, each block after the blocks its rays come from).  Work

@@ -23,7 +23,8 @@ EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_sweep_range", "art_sweep_stats", "art_set_tuning", "art_get_tuning",
            "art_batch_create", "art_batch_launch", "art_batch_stats", "art_batch_destroy",
            "art_ndirs", "art_last_error", "art_autotune", "art_set_heating", "art_schedule",
-           "art_autotune_class", "art_tune_cache")
+           "art_autotune_class", "art_tune_cache", "art_sweep_batched", "art_graph_launch",
+           "art_graph_destroy")
 # include/art_nn.h: layers of the learned surrogate
 NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
@@ -110,6 +111,10 @@ def load(path: str = LIB_PATH):
     L.art_autotune_class.argtypes = [vp, i, ctypes.POINTER(Tuning), i, ctypes.POINTER(Tuning),
                                      ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i), vp]
     L.art_tune_cache.argtypes = [i, ctypes.c_char_p]
+    L.art_sweep_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i), i, ctypes.POINTER(vp),
+                                    ctypes.POINTER(Outputs), ctypes.POINTER(vp), vp]
+    L.art_graph_launch.argtypes = [vp, vp]
+    L.art_graph_destroy.argtypes = [vp]
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]

@@ -1060,4 +1060,23 @@ int art_batch_destroy(art_batch *B)
     return ART_OK;
 }
 
+int art_sweep_batched(art_mesh *const *meshes, const int *nside, int n, const float *const *gamma_w,
+                      const art_outputs *outs, art_graph **graph, void *hip_stream)
+{
+    if (!graph) return fail(ART_E_INVAL, "art_sweep_batched: graph is NULL");
+    art_batch *B = nullptr;
+    int rc = art_batch_create(meshes, nside, n, gamma_w, 0.0f, outs, 1, &B, hip_stream);
+    if (rc) return rc;
+    if ((rc = art_batch_launch(B, hip_stream))) {
+        batch_free(B);
+        return rc;
+    }
+    *graph = B;
+    return ART_OK;
+}
+
+int art_graph_launch(art_graph *graph, void *hip_stream) { return art_batch_launch(graph, hip_stream); }
+
+int art_graph_destroy(art_graph *graph) { return art_batch_destroy(graph); }
+
 }  // extern "C"
