@@ -515,6 +515,8 @@ def main():
                     help="measure point-source RT (128^3, 16 sources) instead of the 256^3 sweep")
     ap.add_argument("--sg-fields", type=int, default=64, help="training fields of --surrogate")
     ap.add_argument("--sg-steps", type=int, default=4800, help="training steps of --surrogate")
+    ap.add_argument("--release-cost", action="store_true",
+                    help="measure the cost of agent-scope release/acquire per workgroup")
     ap.add_argument("--chem", action="store_true",
                     help="measure the chemistry and energy update (128^3) instead of the 256^3 sweep")
     args = ap.parse_args()
@@ -541,6 +543,11 @@ def main():
         return
     if args.point:
         bench_point(steps=args.steps, cpu=not args.no_cpu_baseline)
+        return
+    if args.release_cost:
+        rows = [dict(words=w, **art.release_cost(40000, w)) for w in (256, 1024, 4096)]
+        print(json.dumps({"metric": "ns per workgroup (40000 one-wave workgroups, best of 5)",
+                          "rows": rows}), flush=True)
         return
     if args.chem:
         bench_chem(steps=args.steps, cpu=not args.no_cpu_baseline)

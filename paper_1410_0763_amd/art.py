@@ -40,6 +40,8 @@ SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_
 PT_EXPORTS = ("art_point_sources", "art_point_sources_noalloc")
 # include/art_chem.h: chemistry and energy update of a radiative step
 CHEM_EXPORTS = ("art_chem_step",)
+# include/art_diag.h: measurements behind design decisions
+DIAG_EXPORTS = ("art_diag_release_cost",)
 
 
 class ArtError(RuntimeError):
@@ -152,7 +154,8 @@ def load(path: str = LIB_PATH):
     L.art_point_sources_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
     L.art_chem_step.argtypes = [ctypes.c_longlong, vp, vp, vp, vp, vp, vp, d,
                                 ctypes.POINTER(ChemParams), vp, vp, vp]
-    for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS + CHEM_EXPORTS:
+    L.art_diag_release_cost.argtypes = [i, i, ctypes.POINTER(ctypes.c_float)]
+    for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS + CHEM_EXPORTS + DIAG_EXPORTS:
         if name != "art_last_error":
             getattr(L, name).restype = i
     _lib = L
@@ -377,6 +380,15 @@ def chem_step(n_H, rho, Gamma, Heat, x_HI, u, dt, tables, logT_min, dlogT, T_per
     _check(load().art_chem_step(int(n_H.numel()), _ptr(n_H), _ptr(rho), _ptr(Gamma), _ptr(Heat),
                                 _ptr(x_HI), _ptr(u), float(dt), ctypes.byref(prm), _ptr(dt_chem),
                                 _ptr(nsub), _stream_ptr(stream)))
+
+
+def release_cost(nwg=40000, words=1024):
+    """art_diag_release_cost: ns per workgroup for stores only, a device
+    fence, an agent-scope release store, a relaxed store, an acquire load."""
+    ns = (ctypes.c_float * 5)()
+    _check(load().art_diag_release_cost(int(nwg), int(words), ns))
+    return dict(zip(("stores", "fence", "release_store", "relaxed_store", "acquire_load"),
+                    [float(v) for v in ns]))
 
 
 def tune_cache(op: str, path=None):

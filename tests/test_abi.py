@@ -36,6 +36,14 @@ def test_point_header_and_binding_agree():
     assert _declared("art_point.h") == sorted(art.PT_EXPORTS)
 
 
+def test_diag_header_and_binding_agree():
+    from paper_1410_0763_amd import art
+    assert _declared("art_diag.h") == sorted(art.DIAG_EXPORTS)
+    L = art.load()
+    ns = (ctypes.c_float * 5)()
+    assert L.art_diag_release_cost(0, 16, ns) == -1 and L.art_diag_release_cost(4, 16, None) == -1
+
+
 def test_chem_header_and_binding_agree():
     from paper_1410_0763_amd import art
     assert _declared("art_chem.h") == sorted(art.CHEM_EXPORTS)
@@ -45,7 +53,7 @@ def test_library_exports_every_declared_symbol():
     from paper_1410_0763_amd import art
     L = art.load()
     for name in (_declared() + _declared("art_nn.h") + _declared("art_surrogate.h") +
-                 _declared("art_point.h") + _declared("art_chem.h")):
+                 _declared("art_point.h") + _declared("art_chem.h") + _declared("art_diag.h")):
         assert hasattr(L, name), name
 
 
