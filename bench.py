@@ -356,6 +356,12 @@ def bench_surrogate(train_fields=64, steps=4800, lam=1.0, test_fields=8):
     wf = wk[1][0]
     conv_ms = timed(lambda: nn.conv3d_fwd(xa, 32, wf, b1, shape, 1, y=y), 20)
     conv_flop = 2.0 * 27 * 32 * 32 * V
+    # weight and bias gradients of the same layer (its input xa, the layer
+    # output y standing in for the gradient), workspace partials summed
+    work = torch.zeros(nn.bwd_weight_workspace(32, shape), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((27, 32, 32), dtype=torch.float32, device="cuda")
+    db = torch.zeros(32, dtype=torch.float32, device="cuda")
+    bwdw_ms = timed(lambda: nn.conv3d_bwd_weight(xa, 32, y, shape, work, dw, db), 20)
     rec = {"metric": "surrogate: coarse sweep + inference time against the fine sweep (128^3, Nside 2 -> 16)",
            "value": fine_ms / sur_ms, "unit": "x faster than the fine sweep",
            "surrogate_ms": sur_ms, "fine_sweep_ms": fine_ms, "coarse_sweep_ms": coarse_ms,
@@ -369,6 +375,11 @@ def bench_surrogate(train_fields=64, steps=4800, lam=1.0, test_fields=8):
                         "achieved": conv_flop / (conv_ms / 1e3) / 1e12, "peak": 2500.0,
                         "unit": "TFLOP/s", "frac": conv_flop / (conv_ms / 1e3) / 1e12 / 2500.0,
                         "layer_ms": conv_ms},
+           "weight_gradient": {"kernel": "conv3d_bwd_weight (32->32 layer, 128^3, with the bias and the "
+                                         "partial sums)", "ms": bwdw_ms,
+                               "tflops": conv_flop / (bwdw_ms / 1e3) / 1e12,
+                               "frac": conv_flop / (bwdw_ms / 1e3) / 1e12 / 2500.0},
+           "train_step_ms": train_s / steps * 1e3,
            "config": {"workload": f"128^3 lognormal sigma_ln 1.5 + 16 spheres, 1 bin; {train_fields} "
                                   f"training fields (seeds 5000+i), {test_fields} held-out (6000+i)"}}
     mesh.close()

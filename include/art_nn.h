@@ -34,30 +34,25 @@ extern "C" {
 int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, int D, int H,
                    int W, int relu, void *y, float *y0, void *hip_stream);
 
-/* Weight gradient dw[tap][ci][co] = sum_v x[v + offset(tap)][ci] g[v][co].
- * xs: bf16 [3][cin][V], the channels-first copies of the layer input made
- * by art_nn_shift3; g: bf16 [32][V], the channels-first gradient at the
- * layer output (art_nn_relu_grad).  partial: float32 scratch
- * [nchunk][27][cin][32]; nchunk must divide D*H.  dw: float32 [27][cin][32].
- * W must be a multiple of 16. */
-int art_conv3d_bwd_weight(const void *xs, int cin, const void *g, int D, int H, int W,
-                          float *partial, int nchunk, float *dw, void *hip_stream);
+/* Weight and bias gradients of one layer:
+ * dw[tap][ci][co] = sum_v x[v + offset(tap)][ci] g[v][co] (zero padding) and
+ * db[co] = sum_v g[v][co].  x: bf16 [V][cin], the layer input (cin = 16 or
+ * 32); g: bf16 [V][32], the gradient at the layer output (art_nn_relu_grad).
+ * work: float32 workspace of work_floats >= art_conv3d_bwd_weight_workspace()
+ * elements (per-workgroup partial sums, overwritten).  dw: float32
+ * [27][cin][32]; db: float32 [32] or NULL.  W must be a multiple of 16.
+ * ART_E_INVAL on null pointers, bad sizes or a short workspace. */
+int art_conv3d_bwd_weight(const void *x, int cin, const void *g, int D, int H, int W, float *work,
+                          long long work_floats, float *dw, float *db, void *hip_stream);
 
-/* Bias gradient db[co] = sum_v g[co][v] of a channels-first bf16 gradient
- * [32][V]; partial: float32 scratch [nchunk][32]; nchunk must divide V. */
-int art_nn_bias_grad(const void *g, int V, float *partial, int nchunk, float *db,
-                     void *hip_stream);
-
-/* xs[s][c][v] = x[v + (s - 1) along x][c] (zero outside the mesh), s = 0..2:
- * the channels-first copies the weight gradient reads.  x: bf16 [V][cin],
- * cin = 16 or 32. */
-int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *hip_stream);
+/* Float32 elements of workspace art_conv3d_bwd_weight needs for this shape
+ * (-1 for a shape it rejects).  Host only. */
+long long art_conv3d_bwd_weight_workspace(int cin, int D, int H, int W);
 
 /* Gradient at a layer output: g = dy where y > 0 (the ReLU of the forward
- * pass; y = NULL for the last layer, which has none), else 0.  dy, y: bf16
- * [V][32].  Writes g (bf16 [V][32], channels-last) and g_cf (bf16 [32][V]). */
-int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *g_cf,
-                     void *hip_stream);
+ * pass; y = NULL for the last layer, which has none), else 0.  dy, y, g:
+ * bf16 [V][32]. */
+int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *hip_stream);
 
 /* Matrix-core copies of one layer's weights w (float32 [27][cin][32]):
  * w_fwd bf16 [27][32][cin] for the forward convolution and w_bwd bf16

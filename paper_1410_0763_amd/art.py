@@ -26,7 +26,7 @@ EXPORTS = ("art_create_mesh", "art_destroy_mesh", "art_set_fields", "art_sweep",
            "art_autotune_class", "art_tune_cache", "art_sweep_batched", "art_graph_launch",
            "art_graph_destroy")
 # include/art_nn.h: layers of the learned surrogate
-NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_nn_bias_grad", "art_nn_shift3",
+NN_EXPORTS = ("art_conv3d_fwd", "art_conv3d_bwd_weight", "art_conv3d_bwd_weight_workspace",
               "art_nn_relu_grad", "art_nn_prep_weights", "art_nn_mse", "art_nn_adamw",
               "art_nn_features", "art_nn_expand", "art_nn_log_ratio", "art_nn_ood_count",
               "art_nn_sq_weights")
@@ -120,10 +120,10 @@ def load(path: str = LIB_PATH):
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
     L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
-    L.art_conv3d_bwd_weight.argtypes = [vp, i, vp, i, i, i, vp, i, vp, vp]
-    L.art_nn_bias_grad.argtypes = [vp, i, vp, i, vp, vp]
-    L.art_nn_shift3.argtypes = [vp, i, i, i, i, vp, vp]
-    L.art_nn_relu_grad.argtypes = [vp, vp, i, vp, vp, vp]
+    L.art_conv3d_bwd_weight.argtypes = [vp, i, vp, i, i, i, vp, ctypes.c_longlong, vp, vp, vp]
+    L.art_conv3d_bwd_weight_workspace.argtypes = [i, i, i, i]
+    L.art_conv3d_bwd_weight_workspace.restype = ctypes.c_longlong
+    L.art_nn_relu_grad.argtypes = [vp, vp, i, vp, vp]
     L.art_nn_prep_weights.argtypes = [vp, i, vp, vp, vp]
     L.art_nn_mse.argtypes = [vp, vp, vp, i, vp, vp, vp, vp]
     L.art_nn_sq_weights.argtypes = [vp, i, f, vp, vp, vp]
@@ -478,25 +478,23 @@ class nn:
                                      _ptr(y), _ptr(y0), _stream_ptr(stream)))
 
     @staticmethod
-    def conv3d_bwd_weight(xs, cin, g_cf, shape, partial, nchunk, dw, stream=None):
+    def bwd_weight_workspace(cin, shape):
+        """Float32 elements of workspace conv3d_bwd_weight needs."""
         D, H, W = shape
-        _check(load().art_conv3d_bwd_weight(_ptr(xs), cin, _ptr(g_cf), D, H, W, _ptr(partial),
-                                            nchunk, _ptr(dw), _stream_ptr(stream)))
+        n = load().art_conv3d_bwd_weight_workspace(cin, D, H, W)
+        if n < 0:
+            raise ValueError(f"conv3d_bwd_weight: unsupported shape {shape} with cin {cin}")
+        return int(n)
 
     @staticmethod
-    def bias_grad(g_cf, V, partial, nchunk, db, stream=None):
-        _check(load().art_nn_bias_grad(_ptr(g_cf), V, _ptr(partial), nchunk, _ptr(db),
-                                       _stream_ptr(stream)))
-
-    @staticmethod
-    def shift3(x, cin, shape, xs, stream=None):
+    def conv3d_bwd_weight(x, cin, g, shape, work, dw, db=None, stream=None):
         D, H, W = shape
-        _check(load().art_nn_shift3(_ptr(x), cin, D, H, W, _ptr(xs), _stream_ptr(stream)))
+        _check(load().art_conv3d_bwd_weight(_ptr(x), cin, _ptr(g), D, H, W, _ptr(work), work.numel(),
+                                            _ptr(dw), _ptr(db), _stream_ptr(stream)))
 
     @staticmethod
-    def relu_grad(dy, y, V, g, g_cf, stream=None):
-        _check(load().art_nn_relu_grad(_ptr(dy), _ptr(y), V, _ptr(g), _ptr(g_cf),
-                                       _stream_ptr(stream)))
+    def relu_grad(dy, y, V, g, stream=None):
+        _check(load().art_nn_relu_grad(_ptr(dy), _ptr(y), V, _ptr(g), _stream_ptr(stream)))
 
     @staticmethod
     def prep_weights(w, cin, w_fwd, w_bwd, stream=None):

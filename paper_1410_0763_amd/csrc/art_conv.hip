@@ -15,11 +15,9 @@
 // that every lane stores whole 16-byte runs of one voxel's channels.
 //
 // Weight gradient: dw[tap] = X_tap^T G is a reduction over voxels, so the
-// voxels are the K dimension.  The operands are channels-first copies (one
-// 16-byte load = 8 consecutive voxels of one channel); the x offset of a tap
-// would misalign them, so the layer input is kept as three copies shifted by
-// -1, 0, +1 along x.  Each wave reduces one (tap, chunk of rows) into a
-// float32 partial; a second kernel sums the chunks in a fixed order.
+// voxels are the K dimension of the products; the channels-last operands
+// are transposed into LDS as they are staged (see conv_bwdw_kernel), and
+// the per-workgroup partials are added in a fixed order.
 #include <cstdint>
 
 #include "../../include/art.h"
@@ -166,114 +164,265 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
     }
 }
 
-// One wave: the three taps dx = -1, 0, 1 of one (dz, dy) over one chunk of
-// rows; the gradient operand is loaded once per K step for three MFMAs.
-template <int CIN>
-__global__ __launch_bounds__(256) void conv_bwdw_kernel(const uint16_t *__restrict__ xs,
-                                                        const uint16_t *__restrict__ g, int D,
-                                                        int H, int W, int nchunk,
-                                                        float *__restrict__ partial)
+// Weight and bias gradients.  A workgroup owns one row of TX voxels along x
+// (one y, one x tile) and marches over a chunk of z planes.  LDS holds the
+// input rows y-1 .. y+1 of the planes z-1 .. z+2 (a ring of four slots, one
+// voxel of halo at each end along x) and the gradient rows of planes z and
+// z+1 (two buffers), transposed on the way in so that one 16-byte read gives a lane eight
+// voxels of one channel: voxel x0 + k + j S (j = 0..7, S = TX / 8) is element
+// j of group k.  The eight voxels of a group are S apart, so the x offset of
+// a tap only moves to the neighbouring group (k - 1 or k + 1) and every read
+// stays aligned; groups k = -1 and k = S hold the halo.  Nine waves, one per
+// (dz, dy), keep their three dx taps in float32 accumulators for the whole
+// march.  Each step writes the plane loaded during the previous step into
+// the free slot, issues the loads of the plane after it, and runs the
+// products of plane z: the loads have a whole step to arrive and one
+// barrier per step suffices.  The bias gradient is summed from the staged
+// gradient rows.  Each workgroup writes one float32 partial of all 27 taps
+// and the bias; a second kernel adds the partials in a fixed order.
+constexpr int BW_WAVES = 9, BW_THREADS = 64 * BW_WAVES, BW_SMAX = 16;
+constexpr int BW_CSX = (3 * (BW_SMAX + 2)) | 1;   // 16-byte groups per channel of an input slot (odd)
+constexpr int BW_CSG = BW_SMAX | 1;               // 16-byte groups per channel of the gradient row
+// LDS: four input slots, two gradient buffers, the bias sums [32][S] (float)
+template <int CIN> constexpr int bw_lds_bytes() { return (4 * CIN * BW_CSX + 2 * 32 * BW_CSG) * 16 + 32 * BW_SMAX * 4; }
+
+// Keeps the loads of the next plane after the LDS writes of the previous one
+// (both sets of registers live at once would spill).
+__device__ __forceinline__ void bw_order()
 {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Eight voxels (one 16-byte load each: eight channels) -> eight channels
+// (one 16-byte group each: the eight voxels); one byte permute per dword
+// (selector bytes 0-3 take the second operand, 4-7 the first).
+__device__ __forceinline__ void bw_transpose(const u32x4 (&in)[8], u32x4 (&out)[8])
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            out[e][q] = __builtin_amdgcn_perm(in[2 * q + 1][e >> 1], in[2 * q][e >> 1],
+                                              (e & 1) ? 0x07060302u : 0x05040100u);
+}
+
+// Wave roles.  Waves 0-8 each own the taps of one (dz, dy) = (w / 3 - 1,
+// w % 3 - 1).  Staging: wave 1 stages the gradient row (and sums the bias),
+// waves 2, 3, 6 and 7 the input rows; with the usual round-robin placement
+// of waves on the four SIMDs (w % 4), the SIMD that holds three product
+// waves (0, 4, 8) does no staging.
+__device__ __forceinline__ int bw_xstager(int wave)
+{
+    return wave == 2 ? 0 : wave == 3 ? 1 : wave == 6 ? 2 : wave == 7 ? 3 : -1;
+}
+
+template <int CIN, int S>
+__global__ __launch_bounds__(BW_THREADS) void conv_bwdw_kernel(const uint16_t *__restrict__ x,
+                                                               const uint16_t *__restrict__ g, int D,
+                                                               int H, int W, int ntx,
+                                                               int planes, int nwg, int remap,
+                                                               float *__restrict__ partial)
+{
+    extern __shared__ __align__(16) u32x4 lds[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long job = (long long)blockIdx.x * 4 + wave;
-    if (job >= 9ll * nchunk) return;                       // whole wave
-    const int zy = (int)(job % 9), chunk = (int)(job / 9);
-    const int dz = zy / 3 - 1, dy = zy % 3 - 1;
     const int m = lane & 31, kh = lane >> 5;
+    // workgroups that handle neighbouring rows share an XCD (and its L2)
+    const int b = (int)blockIdx.x;
+    const int L = remap ? (b & 7) * (nwg >> 3) + (b >> 3) : b;
+    const int rows = H * ntx;
+    const int row = L % rows, chunk = L / rows;
+    const int y = row % H, x0 = (row / H) * (8 * S);
+    const int z0 = chunk * planes, z1 = min(D, z0 + planes);
     const long long V = (long long)D * H * W;
-    const rsrc_t rX = nn_rsrc(xs, 3ll * CIN * V * 2);
-    const rsrc_t rG = nn_rsrc(g, 32ll * V * 2);
-    const long long gbase = (long long)m * V;
-    const int rows = D * H / nchunk;
+    const rsrc_t rX = nn_rsrc(x, V * CIN * 2);
+    const rsrc_t rG = nn_rsrc(g, V * 64);
+    const int GB = 4 * CIN * BW_CSX;                          // first group of the gradient rows
+
+    // this thread's staging task: a gradient group (kk < S, channels c8 ..
+    // c8 + 7) or an input group (row r of a slot, kk in [0, S + 2)); the kind
+    // is uniform over a wave
+    const bool isg = wave == 1;
+    const int xw = bw_xstager(wave);
+    const int nxt = 3 * (S + 2) * (CIN / 8), per = (nxt + 3) / 4;
+    const int task = isg ? lane : xw * per + lane;
+    const bool has = isg ? lane < 4 * S : xw >= 0 && lane < per && task < nxt;
+    int tr = 0, tkk = 0, tc8 = 0;
+    if (isg) {
+        tkk = task % S;
+        tc8 = 8 * (task / S);
+    } else {
+        tkk = task % (S + 2);
+        tr = (task / (S + 2)) % 3;
+        tc8 = 8 * (task / (3 * (S + 2)));
+    }
+    // voxel x of element j: xj0 + j S; only j = 0 (left halo) and j = 7
+    // (right halo) can leave the mesh
+    const int xj0 = isg ? x0 + tkk : x0 + tkk - 1;
+    const bool okl = xj0 >= 0, okr = xj0 + 7 * S < W;
+    constexpr int CH = 32;                                    // channels of the gradient
+    u32x4 ld[8];
+    float *bacc = reinterpret_cast<float *>(lds + GB + 2 * 32 * BW_CSG);   // bias sums [32][S]
+    if (isg && has)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bacc[(tc8 + e) * S + tkk] = 0.0f;
+
+    auto load = [&](int p) {                                  // plane p of the task's array
+        if (!has) return;
+        const int yy = isg ? y : y + tr - 1;
+        const bool inrow = p >= 0 && p < D && yy >= 0 && yy < H;
+        const long long v0 = ((long long)p * H + yy) * W + xj0;
+        if (isg) {
+            const unsigned o = inrow ? (unsigned)((v0 * CH + tc8) * 2) : NN_OOB;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ld[j] = __builtin_amdgcn_raw_buffer_load_b128(rG, o + j * S * CH * 2, 0, 0);
+        } else {
+            const unsigned o = inrow ? (unsigned)((v0 * CIN + tc8) * 2) : NN_OOB;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool ok = j == 0 ? okl : j == 7 ? okr : true;
+                ld[j] = __builtin_amdgcn_raw_buffer_load_b128(rX, ok ? o + j * S * CIN * 2 : NN_OOB, 0, 0);
+            }
+        }
+    };
+    auto store = [&](int slot) {                              // transpose into LDS (x slot or g buffer)
+        if (!has) return;
+        u32x4 t[8];
+        bw_transpose(ld, t);
+        if (isg) {
+            u32x4 *dst = lds + GB + (slot * 32 + tc8) * BW_CSG + tkk;
+            float *bs = bacc + tc8 * S + tkk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                dst[e * BW_CSG] = t[e];
+                float s4[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    s4[q] = __uint_as_float(t[e][q] << 16) + __uint_as_float(t[e][q] & 0xffff0000u);
+                bs[e * S] += (s4[0] + s4[1]) + (s4[2] + s4[3]);
+            }
+        } else {
+            u32x4 *dst = lds + (slot * CIN + tc8) * BW_CSX + tr * (S + 2) + tkk;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[e * BW_CSX] = t[e];
+        }
+    };
+    auto slot_of = [&](int p) { return (p - z0 + 1) & 3; };
+    auto gbuf_of = [&](int p) { return (p - z0) & 1; };
+
+    // prologue: input planes z0 - 1 .. z0 + 1 and the gradient row of z0 in
+    // LDS, the next plane (input z0 + 2, gradient z0 + 1) in registers
+    if (isg) {
+        load(z0);
+        store(0);
+    } else {
+        for (int p = z0 - 1; p <= z0 + 1; ++p) {
+            load(p);
+            store(slot_of(p));
+            bw_order();
+        }
+    }
+    bw_order();
+    if (z0 + 1 < z1) load(isg ? z0 + 1 : z0 + 2);
+    __syncthreads();
+
+    const int dz = wave / 3 - 1, dy = wave % 3 - 1;
     f32x16 acc[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) acc[s] = f32x16{};
-    for (int r = chunk * rows; r < (chunk + 1) * rows; ++r) {
-        const int z = r / H, yv = r % H;
-        const int zz = z + dz, yy = yv + dy;
-        const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && m < CIN;
-        const long long arow = ((long long)zz * H + yy) * W + 8 * kh;   // within one copy
-        const long long grow = gbase + (long long)r * W + 8 * kh;
-        for (int x0 = 0; x0 < W; x0 += 16) {
-            const bf16x8 b = load8(rG, (unsigned)((grow + x0) * 2));
+    const bool lane_x = CIN == 32 || m < CIN;
+    const bool row_ok = y + dy >= 0 && y + dy < H;
+    for (int z = z0; z < z1; ++z) {
+        // the slot of plane z - 2 and the gradient buffer of z - 1 are free
+        if (z + 1 < z1) store(isg ? gbuf_of(z + 1) : slot_of(z + 2));
+        bw_order();
+        if (z + 2 < z1) load(isg ? z + 2 : z + 3);
+        const int p = z + dz;
+        if (row_ok && p >= 0 && p < D) {                      // uniform over the wave
+            const u32x4 *xa = lds + (slot_of(p) * CIN + m) * BW_CSX + (dy + 1) * (S + 2) + kh;
+            const u32x4 *ga = lds + GB + (gbuf_of(z) * 32 + m) * BW_CSG + kh;
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const long long aoff = ((long long)s * CIN + m) * V + arow + x0;
-                const bf16x8 a = load8(rX, ok ? (unsigned)(aoff * 2) : NN_OOB);
-                acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[s], 0, 0, 0);
+            for (int kb = 0; kb < S; kb += 2) {
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, ga[kb]);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    const bf16x8 av = lane_x ? __builtin_bit_cast(bf16x8, xa[kb + s]) : bf16x8{};
+                    acc[s] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[s], 0, 0, 0);
+                }
             }
         }
+        __syncthreads();
     }
+
+    const int nper = 27 * CIN * 32 + 32;
+    float *out = partial + (long long)L * nper;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int tap = zy * 3 + s;
+        const int tap = wave * 3 + s;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int ci = acc_row(q, lane);
-            if (ci < CIN) partial[(((long long)chunk * 27 + tap) * CIN + ci) * 32 + m] = acc[s][q];
+            if (ci < CIN) out[(tap * CIN + ci) * 32 + m] = acc[s][q];
         }
     }
-}
-
-__global__ void sum_chunks_kernel(const float *__restrict__ partial, int nchunk, int n,
-                                  float *__restrict__ out)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int c = 0; c < nchunk; ++c) s += partial[(long long)c * n + i];
-    out[i] = s;
-}
-
-// Per-chunk channel sums of a channels-first [32][V] bf16 array (fixed tree order).
-__global__ __launch_bounds__(256) void bias_partial_kernel(const uint16_t *__restrict__ g,
-                                                           long long V, int nchunk,
-                                                           float *__restrict__ partial)
-{
-    __shared__ float red[256];
-    const int chunk = blockIdx.x;
-    const long long len = V / nchunk, v0 = chunk * len;
-    for (int c = 0; c < 32; ++c) {
+    // bias: the gradient tasks' sums, added over k in order (the loop's last
+    // barrier has made them visible)
+    if (threadIdx.x < 32) {
         float s = 0.0f;
-        for (long long v = threadIdx.x; v < len; v += 256) s += bf2f(g[c * V + v0 + v]);
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int k = 128; k > 0; k >>= 1) {
-            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) partial[chunk * 32 + c] = red[0];
-        __syncthreads();
-    }
-}
-
-// One thread per (voxel, group of 8 channels): a 16-byte load of the
-// channels-last input, eight 2-byte stores into each channels-first copy.
-__global__ void shift3_kernel(const uint16_t *__restrict__ x, int cin, int W, long long V,
-                              uint16_t *__restrict__ xs)
-{
-    const int ng = cin / 8;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= V * ng) return;
-    const long long v = t / ng;
-    const int cg = (int)(t % ng);
-    const int xx = (int)(v % W);
-    for (int s = 0; s < 3; ++s) {
-        const int sx = xx + s - 1;
-        u32x4 d = {0u, 0u, 0u, 0u};
-        if (sx >= 0 && sx < W) d = *reinterpret_cast<const u32x4 *>(x + (v + s - 1) * cin + 8 * cg);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const unsigned word = d[e >> 1];
-            xs[((long long)s * cin + 8 * cg + e) * V + v] = (uint16_t)((e & 1) ? (word >> 16) : (word & 0xffffu));
-        }
+        for (int k = 0; k < S; ++k) s += bacc[threadIdx.x * S + k];
+        out[27 * CIN * 32 + threadIdx.x] = s;
     }
 }
 
-// One thread per (voxel, group of 8 channels): 16-byte loads and store of the
-// channels-last arrays, eight 2-byte stores into the channels-first copy.
+// out[i] = sum over the partials p of partial[p][i]: wave w adds p = w, w + 8,
+// ... in order, then the eight wave sums are added pairwise.
+__global__ __launch_bounds__(512) void bw_reduce_kernel(const float *__restrict__ partial, int np, int n,
+                                                        int ndw, float *__restrict__ dw,
+                                                        float *__restrict__ db)
+{
+    __shared__ float red[8][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (i < n) {
+#pragma unroll 8
+        for (int p = wave; p < np; p += 8) s += partial[(long long)p * n + i];
+    }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && i < n) {
+        const float t = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
+                        ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]));
+        if (i < ndw) dw[i] = t;
+        else if (db) db[i - ndw] = t;
+    }
+}
+
+// Workgroup layout of the weight gradient: x tiles of TX = 128, 64, 32 or 16
+// voxels (the largest dividing W), rows (y, x tile), and chunks of z planes
+// so that about 256 workgroups (one per compute unit) run.
+struct BwPlan {
+    int S, ntx, planes, nwg;
+};
+BwPlan bw_plan(int D, int H, int W)
+{
+    BwPlan p{};
+    const int tx = W % 128 == 0 ? 128 : W % 64 == 0 ? 64 : W % 32 == 0 ? 32 : 16;
+    p.S = tx / 8;
+    p.ntx = W / tx;
+    const long long rows = (long long)H * p.ntx;
+    long long zc = (256 + rows - 1) / rows;
+    zc = zc < 1 ? 1 : zc > D ? D : zc;
+    p.planes = (int)((D + zc - 1) / zc);
+    zc = (D + p.planes - 1) / p.planes;
+    p.nwg = (int)(rows * zc);
+    return p;
+}
+
+// One thread per (voxel, group of 8 channels): 16-byte loads and store.
 __global__ void relu_grad_kernel(const uint16_t *__restrict__ dy, const uint16_t *__restrict__ y,
-                                 long long V, uint16_t *__restrict__ g, uint16_t *__restrict__ gcf)
+                                 long long V, uint16_t *__restrict__ g)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= V * 4) return;
@@ -290,11 +439,6 @@ __global__ void relu_grad_kernel(const uint16_t *__restrict__ dy, const uint16_t
         }
     }
     *reinterpret_cast<u32x4 *>(g + v * 32 + 8 * cg) = d;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const unsigned word = d[e >> 1];
-        gcf[(long long)(8 * cg + e) * V + v] = (uint16_t)((e & 1) ? (word >> 16) : (word & 0xffffu));
-    }
 }
 
 __global__ void prep_weights_kernel(const float *__restrict__ w, int cin, uint16_t *__restrict__ wf,
@@ -462,6 +606,37 @@ int launch_status(const char *what)
 
 unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// One instantiation per (cin, S); the LDS opt-in above 64 KiB is made once
+// per instantiation.
+template <int CIN, int S>
+int bw_launch_s(const BwPlan &p, const uint16_t *x, const uint16_t *g, int D, int H, int W, float *work,
+                hipStream_t st)
+{
+    static bool configured = false;
+    if (!configured) {
+        const hipError_t e = hipFuncSetAttribute((const void *)conv_bwdw_kernel<CIN, S>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, bw_lds_bytes<CIN>());
+        if (e != hipSuccess)
+            return art_set_error(ART_E_HIP, (std::string("art_conv3d_bwd_weight: ") + hipGetErrorString(e)).c_str());
+        configured = true;
+    }
+    hipLaunchKernelGGL((conv_bwdw_kernel<CIN, S>), dim3(p.nwg), dim3(BW_THREADS), bw_lds_bytes<CIN>(), st, x, g, D,
+                       H, W, p.ntx, p.planes, p.nwg, (int)(p.nwg % 8 == 0), work);
+    return ART_OK;
+}
+
+template <int CIN>
+int bw_launch(const BwPlan &p, const uint16_t *x, const uint16_t *g, int D, int H, int W, float *work,
+              hipStream_t st)
+{
+    switch (p.S) {
+    case 2: return bw_launch_s<CIN, 2>(p, x, g, D, H, W, work, st);
+    case 4: return bw_launch_s<CIN, 4>(p, x, g, D, H, W, work, st);
+    case 8: return bw_launch_s<CIN, 8>(p, x, g, D, H, W, work, st);
+    default: return bw_launch_s<CIN, 16>(p, x, g, D, H, W, work, st);
+    }
+}
+
 __global__ void art_fill_u32_kernel_entry(unsigned int *p) { *p = 0u; }
 
 }  // namespace
@@ -501,61 +676,44 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
     return launch_status("art_conv3d_fwd");
 }
 
-int art_conv3d_bwd_weight(const void *xs, int cin, const void *g, int D, int H, int W,
-                          float *partial, int nchunk, float *dw, void *hip_stream)
+long long art_conv3d_bwd_weight_workspace(int cin, int D, int H, int W)
 {
-    if (!xs || !g || !partial || !dw) return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: null pointer");
+    if ((cin != 16 && cin != 32) || D < 1 || H < 1 || W < 16 || W % 16) return -1;
+    const BwPlan p = bw_plan(D, H, W);
+    return (long long)p.nwg * (27 * cin * 32 + 32);
+}
+
+int art_conv3d_bwd_weight(const void *x, int cin, const void *g, int D, int H, int W, float *work,
+                          long long work_floats, float *dw, float *db, void *hip_stream)
+{
+    if (!x || !g || !work || !dw) return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: null pointer");
     if (cin != 16 && cin != 32) return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: cin must be 16 or 32");
     if (D < 1 || H < 1 || W < 16 || W % 16)
         return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: W must be a positive multiple of 16");
-    if (nchunk < 1 || (D * H) % nchunk)
-        return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: nchunk must divide D*H");
-    if (3ll * cin * D * H * W * 2 >= (1ll << 31))
-        return art_set_error(ART_E_UNSUPPORTED, "art_conv3d_bwd_weight: shifted copies above 2 GiB");
+    if ((long long)D * H * W * 64 >= (1ll << 31))
+        return art_set_error(ART_E_UNSUPPORTED, "art_conv3d_bwd_weight: gradient tensor above 2 GiB");
+    const BwPlan p = bw_plan(D, H, W);
+    const int n = 27 * cin * 32 + 32;
+    if (work_floats < (long long)p.nwg * n)
+        return art_set_error(ART_E_INVAL, "art_conv3d_bwd_weight: workspace smaller than "
+                                          "art_conv3d_bwd_weight_workspace()");
     hipStream_t st = (hipStream_t)hip_stream;
-    const auto *xp = (const uint16_t *)xs;
+    const auto *xp = (const uint16_t *)x;
     const auto *gp = (const uint16_t *)g;
-    const unsigned nb = blocks_for(9ll * nchunk, 4);
-    if (cin == 16)
-        hipLaunchKernelGGL(conv_bwdw_kernel<16>, dim3(nb), dim3(256), 0, st, xp, gp, D, H, W, nchunk, partial);
-    else
-        hipLaunchKernelGGL(conv_bwdw_kernel<32>, dim3(nb), dim3(256), 0, st, xp, gp, D, H, W, nchunk, partial);
-    int rc = launch_status("art_conv3d_bwd_weight");
+    int rc = cin == 16 ? bw_launch<16>(p, xp, gp, D, H, W, work, st) : bw_launch<32>(p, xp, gp, D, H, W, work, st);
     if (rc) return rc;
-    const int n = 27 * cin * 32;
-    hipLaunchKernelGGL(sum_chunks_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, partial, nchunk, n, dw);
+    rc = launch_status("art_conv3d_bwd_weight");
+    if (rc) return rc;
+    hipLaunchKernelGGL(bw_reduce_kernel, dim3(blocks_for(n, 64)), dim3(512), 0, st, work, p.nwg, n,
+                       27 * cin * 32, dw, db);
     return launch_status("art_conv3d_bwd_weight (sum)");
 }
 
-int art_nn_bias_grad(const void *g, int V, float *partial, int nchunk, float *db, void *hip_stream)
+int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *hip_stream)
 {
-    if (!g || !partial || !db || V < 1 || nchunk < 1 || V % nchunk)
-        return art_set_error(ART_E_INVAL, "art_nn_bias_grad: bad arguments (nchunk must divide V)");
-    hipStream_t st = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(bias_partial_kernel, dim3(nchunk), dim3(256), 0, st, (const uint16_t *)g,
-                       (long long)V, nchunk, partial);
-    int rc = launch_status("art_nn_bias_grad");
-    if (rc) return rc;
-    hipLaunchKernelGGL(sum_chunks_kernel, dim3(1), dim3(32), 0, st, partial, nchunk, 32, db);
-    return launch_status("art_nn_bias_grad (sum)");
-}
-
-int art_nn_shift3(const void *x, int cin, int D, int H, int W, void *xs, void *hip_stream)
-{
-    if (!x || !xs || (cin != 16 && cin != 32) || D < 1 || H < 1 || W < 1)
-        return art_set_error(ART_E_INVAL, "art_nn_shift3: bad arguments (cin must be 16 or 32)");
-    const long long V = (long long)D * H * W;
-    hipLaunchKernelGGL(shift3_kernel, dim3(blocks_for(V * (cin / 8), 256)), dim3(256), 0, (hipStream_t)hip_stream,
-                       (const uint16_t *)x, cin, W, V, (uint16_t *)xs);
-    return launch_status("art_nn_shift3");
-}
-
-int art_nn_relu_grad(const void *dy, const void *y, int V, void *g, void *g_cf, void *hip_stream)
-{
-    if (!dy || !g || !g_cf || V < 1) return art_set_error(ART_E_INVAL, "art_nn_relu_grad: bad arguments");
+    if (!dy || !g || V < 1) return art_set_error(ART_E_INVAL, "art_nn_relu_grad: bad arguments");
     hipLaunchKernelGGL(relu_grad_kernel, dim3(blocks_for(4ll * V, 256)), dim3(256), 0, (hipStream_t)hip_stream,
-                       (const uint16_t *)dy, (const uint16_t *)y, (long long)V, (uint16_t *)g,
-                       (uint16_t *)g_cf);
+                       (const uint16_t *)dy, (const uint16_t *)y, (long long)V, (uint16_t *)g);
     return launch_status("art_nn_relu_grad");
 }
 

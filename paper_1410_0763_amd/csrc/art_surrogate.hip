@@ -255,7 +255,7 @@ struct Gen {
 struct art_surrogate {
     int D = 0, H = 0, W = 0;
     long long V = 0;
-    int nchunk = 1, nchunk_b = 1;
+    long long nwork = 0;
     int step = 0;
     float mu[3] = {0, 0, 0}, sd[3] = {1, 1, 1};
     float lo[3] = {-INFINITY, -INFINITY, -INFINITY}, hi[3] = {INFINITY, INFINITY, INFINITY};
@@ -264,9 +264,8 @@ struct art_surrogate {
     float *w[NL] = {}, *b[NL] = {}, *mw[NL] = {}, *vw[NL] = {}, *mb[NL] = {}, *vb[NL] = {};
     float *dw[NL] = {}, *db[NL] = {};
     uint16_t *w_fwd[NL] = {}, *w_bwd[NL] = {};
-    uint16_t *acts[NL - 1] = {}, *dy[2] = {}, *g = nullptr, *gcf = nullptr, *xs = nullptr,
-             *x = nullptr;
-    float *pred = nullptr, *partial = nullptr, *bpart = nullptr, *mpart = nullptr,
+    uint16_t *acts[NL - 1] = {}, *dy[2] = {}, *g = nullptr, *x = nullptr;
+    float *pred = nullptr, *work = nullptr, *mpart = nullptr,
           *wpart = nullptr, *loss = nullptr;
     float *Jc = nullptr, *Jexc = nullptr, *Jinc = nullptr, *Jf = nullptr, *Jinf = nullptr;
     unsigned *count = nullptr;
@@ -353,11 +352,7 @@ int art_surrogate_create(int nx, int ny, int nz, unsigned long long seed, art_su
     s->H = ny;
     s->W = nx;
     s->V = V;
-    const long long rows = (long long)nz * ny;
-    for (int c : {512, 256, 128, 64, 32, 16, 8, 4, 2, 1})
-        if (rows % c == 0) { s->nchunk = c; break; }
-    for (int c : {1024, 512, 256, 128, 64, 32, 16, 8, 4, 2, 1})
-        if (V % c == 0) { s->nchunk_b = c; break; }
+    s->nwork = art_conv3d_bwd_weight_workspace(32, nz, ny, nx);   // covers cin = 16 too
     int rc = ART_OK;
     auto A = [&](auto **p, size_t n) {
         if (rc == ART_OK) rc = sg_alloc(s, p, n);
@@ -370,10 +365,9 @@ int art_surrogate_create(int nx, int ny, int nz, unsigned long long seed, art_su
     }
     for (int l = 0; l < NL - 1; ++l) A(&s->acts[l], V * 32);
     A(&s->dy[0], V * 32); A(&s->dy[1], V * 32);
-    A(&s->g, V * 32); A(&s->gcf, V * 32); A(&s->xs, 3 * 32 * V); A(&s->x, V * 16);
+    A(&s->g, V * 32); A(&s->x, V * 16);
     A(&s->pred, V); A(&s->Jc, V); A(&s->Jexc, V); A(&s->Jinc, V); A(&s->Jf, V); A(&s->Jinf, V);
-    A(&s->partial, (size_t)s->nchunk * 27 * 32 * 32);
-    A(&s->bpart, (size_t)s->nchunk_b * 32);
+    A(&s->work, (size_t)s->nwork);
     A(&s->mpart, 256); A(&s->wpart, 257); A(&s->loss, 1); A(&s->count, 1);
     A(&s->spart, (size_t)STAT_BLOCKS * 12);
     if (rc == ART_OK) {
@@ -534,12 +528,10 @@ int art_surrogate_gradients(art_surrogate *s, const void *x, const float *target
     RCCHK(art_nn_mse(s->pred, target, weight, V, s->mpart, loss ? loss : s->loss, s->dy[0], st));
     int cur = 0;
     for (int l = NL - 1; l >= 0; --l) {
-        RCCHK(art_nn_relu_grad(s->dy[cur], l < NL - 1 ? s->acts[l] : nullptr, V, s->g, s->gcf, st));
+        RCCHK(art_nn_relu_grad(s->dy[cur], l < NL - 1 ? s->acts[l] : nullptr, V, s->g, st));
         const void *xin = l == 0 ? x : s->acts[l - 1];
-        RCCHK(art_nn_shift3(xin, CIN[l], s->D, s->H, s->W, s->xs, st));
-        RCCHK(art_conv3d_bwd_weight(s->xs, CIN[l], s->gcf, s->D, s->H, s->W, s->partial, s->nchunk,
-                                    s->dw[l], st));
-        RCCHK(art_nn_bias_grad(s->gcf, V, s->bpart, s->nchunk_b, s->db[l], st));
+        RCCHK(art_conv3d_bwd_weight(xin, CIN[l], s->g, s->D, s->H, s->W, s->work, s->nwork, s->dw[l],
+                                    s->db[l], st));
         if (l > 0) {
             RCCHK(art_conv3d_fwd(s->g, 32, s->w_bwd[l], nullptr, s->D, s->H, s->W, 0, s->dy[1 - cur],
                                  nullptr, st));

@@ -136,8 +136,17 @@ def test_nn_argument_checks_without_gpu():
     assert L.art_conv3d_fwd(p, 8, p, None, 4, 4, 32, 1, p, None, None) == -1
     assert L.art_conv3d_fwd(p, 16, p, None, 4, 4, 48, 1, p, None, None) == -1
     assert b"multiple of 32" in L.art_last_error()
-    assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 32, p, 3, p, None) == -1   # 3 does not divide 16
-    assert L.art_nn_bias_grad(p, 100, p, 7, p, None) == -1
+    assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 24, p, 1 << 30, p, None, None) == -1
+    assert b"multiple of 16" in L.art_last_error()
+    need = L.art_conv3d_bwd_weight_workspace(32, 4, 4, 32)
+    assert need == 16 * (27 * 32 * 32 + 32)                  # 4 rows x 4 chunks of 1 plane
+    assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 32, p, need - 1, p, None, None) == -1
+    assert b"workspace" in L.art_last_error()
+    assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 32, None, need, p, None, None) == -1
+    assert L.art_conv3d_bwd_weight_workspace(8, 4, 4, 32) == -1
+    assert L.art_conv3d_bwd_weight_workspace(32, 4, 4, 40) == -1
+    assert L.art_conv3d_bwd_weight_workspace(32, 128, 128, 128) == 256 * (27 * 32 * 32 + 32)
+    assert L.art_nn_relu_grad(None, None, 4, p, None) == -1
     assert L.art_nn_prep_weights(p, 20, p, p, None) == -1
     assert L.art_nn_adamw(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == -1
 

@@ -79,17 +79,12 @@ def test_conv_gradients_match_reference():
         wbw = torch.zeros((27, 32, 32), dtype=torch.int16, device="cuda")
         nn.prep_weights(_dev(w), cin, wf, wbw)
         g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
-        gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
-        nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g, gcf)
-        xs = torch.zeros((3, cin, V), dtype=torch.int16, device="cuda")
-        nn.shift3(_dev(xb.reshape(V, cin)), cin, shape, xs)
-        nchunk = 4
-        part = torch.zeros(nchunk * 27 * cin * 32, dtype=torch.float32, device="cuda")
+        nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g)
+        xd = _dev(xb.reshape(V, cin))
+        work = torch.zeros(nn.bwd_weight_workspace(cin, shape), dtype=torch.float32, device="cuda")
         dw = torch.zeros((27, cin, 32), dtype=torch.float32, device="cuda")
-        nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw)
-        bpart = torch.zeros(nchunk * 32, dtype=torch.float32, device="cuda")
         db = torch.zeros(32, dtype=torch.float32, device="cuda")
-        nn.bias_grad(gcf, V, bpart, nchunk, db)
+        nn.conv3d_bwd_weight(xd, cin, g, shape, work, dw, db)
         dx = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
         nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dx)
         torch.cuda.synchronize()
@@ -101,10 +96,10 @@ def test_conv_gradients_match_reference():
         print(f"cin {cin}: dw {e_dw:.2e}  db {e_db:.2e}  dx (bf16) {e_dx:.2e}", flush=True)
         assert e_dw <= 1e-5 and e_db <= 1e-5 and e_dx <= 4e-3
         # the fixed-order reductions are bitwise reproducible
-        dw2 = torch.zeros_like(dw)
-        nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw2)
+        dw2, db2 = torch.zeros_like(dw), torch.zeros_like(db)
+        nn.conv3d_bwd_weight(xd, cin, g, shape, work, dw2, db2)
         torch.cuda.synchronize()
-        assert torch.equal(dw, dw2)
+        assert torch.equal(dw, dw2) and torch.equal(db, db2)
 
 
 U32 = 2.0 ** -24      # unit roundoff of float32
@@ -138,14 +133,10 @@ def test_conv_multitile_elementwise(cin):
     nn.conv3d_fwd(_dev(xb), cin, wf, _dev(bias), shape, 0, y0=y0)
     # gradients
     g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
-    gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
-    nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g, gcf)
-    xs = torch.zeros((3, cin, V), dtype=torch.int16, device="cuda")
-    nn.shift3(_dev(xb.reshape(V, cin)), cin, shape, xs)
-    nchunk = 8
-    part = torch.zeros(nchunk * 27 * cin * 32, dtype=torch.float32, device="cuda")
+    nn.relu_grad(_dev(gb.reshape(V, 32)), None, V, g)
+    work = torch.zeros(nn.bwd_weight_workspace(cin, shape), dtype=torch.float32, device="cuda")
     dw = torch.zeros((27, cin, 32), dtype=torch.float32, device="cuda")
-    nn.conv3d_bwd_weight(xs, cin, gcf, shape, part, nchunk, dw)
+    nn.conv3d_bwd_weight(_dev(xb.reshape(V, cin)), cin, g, shape, work, dw)
     dx = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
     nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dx)
     torch.cuda.synchronize()
@@ -167,6 +158,84 @@ def test_conv_multitile_elementwise(cin):
     assert ey.max() <= 1.0 and edw.max() <= 1.0 and edx.max() <= 1.0
 
 
+def _dw_db_bounds(xq, gq, dw, db, taps=range(27)):
+    """Largest error of dw (selected taps) and db over the float32
+    accumulation bound n u sum|terms| (n = number of voxels)."""
+    V = gq.shape[0] * gq.shape[1] * gq.shape[2]
+    D, H, W, cin = xq.shape
+    xp = np.zeros((D + 2, H + 2, W + 2, cin))
+    xp[1:-1, 1:-1, 1:-1] = xq
+    g2 = gq.reshape(V, 32)
+    worst = 0.0
+    for t in taps:
+        dz, dy, dx = t // 9 - 1, (t // 3) % 3 - 1, t % 3 - 1
+        xs = xp[1 + dz:1 + dz + D, 1 + dy:1 + dy + H, 1 + dx:1 + dx + W].reshape(V, cin)
+        ref = xs.T @ g2
+        bound = V * U32 * (np.abs(xs).T @ np.abs(g2))
+        worst = max(worst, float(np.max(np.abs(dw[t] - ref) / np.maximum(bound, 1e-300))))
+    rdb = g2.sum(axis=0)
+    eb = float(np.max(np.abs(db - rdb) / np.maximum(V * U32 * np.abs(g2).sum(axis=0), 1e-300)))
+    return worst, eb
+
+
+@pytest.mark.parametrize("cin,shape", [(32, (10, 64, 128)), (16, (5, 6, 48)), (32, (4, 3, 160)),
+                                       (32, (2, 2, 256)), (16, (1, 1, 16)), (32, (7, 1, 32))])
+def test_bwd_weight_tiles_chunks_and_edges(cin, shape):
+    """Weight and bias gradients, every element against FP64 within the
+    float32 accumulation bound: x tiles of 128, 16, 32 and 128 voxels (S = 16,
+    2, 4, 16 groups), several and ragged chunks of z planes per workgroup
+    (10 planes over 4 chunks), single-voxel rows and planes (every tap but the
+    centre reads only padding), and the bitwise repeat."""
+    _case(f"conv3d weight gradient cin {cin} shape {shape}")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    D, H, W = shape
+    V = D * H * W
+    rng = np.random.default_rng(cin * 1000 + V)
+    xb = bf16_bits(rng.normal(size=(D, H, W, cin)))
+    gb = bf16_bits(rng.normal(size=(D, H, W, 32)))
+    work = torch.full((nn.bwd_weight_workspace(cin, shape),), float("nan"), dtype=torch.float32,
+                      device="cuda")
+    dw = torch.full((27, cin, 32), float("nan"), dtype=torch.float32, device="cuda")
+    db = torch.full((32,), float("nan"), dtype=torch.float32, device="cuda")
+    xd, gd = _dev(xb.reshape(V, cin)), _dev(gb.reshape(V, 32))
+    nn.conv3d_bwd_weight(xd, cin, gd, shape, work, dw, db)
+    torch.cuda.synchronize()
+    ew, eb = _dw_db_bounds(bf16_value(xb), bf16_value(gb), dw.cpu().numpy().astype(np.float64),
+                           db.cpu().numpy().astype(np.float64))
+    print(f"dw {ew:.3f}, db {eb:.3f} of their bounds", flush=True)
+    assert ew <= 1.0 and eb <= 1.0
+    dw2, db2 = torch.zeros_like(dw), torch.zeros_like(db)
+    nn.conv3d_bwd_weight(xd, cin, gd, shape, work, dw2, db2)
+    torch.cuda.synchronize()
+    assert torch.equal(dw, dw2) and torch.equal(db, db2)
+
+
+def test_bwd_weight_full_size_128():
+    """The 32 -> 32 layer shape of the surrogate benchmark (128^3, 256
+    workgroups of 64 planes): five taps (the centre and four corners) and
+    the bias against FP64, within the float32 accumulation bound."""
+    _case("conv3d weight gradient cin 32 shape (128, 128, 128)")
+    import torch
+    from paper_1410_0763_amd.art import nn
+    shape = (128, 128, 128)
+    V = 128 ** 3
+    rng = np.random.default_rng(4242)
+    xb = bf16_bits(rng.normal(size=(V, 32)).astype(np.float32))
+    gb = bf16_bits(rng.normal(size=(V, 32)).astype(np.float32))
+    work = torch.zeros(nn.bwd_weight_workspace(32, shape), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((27, 32, 32), dtype=torch.float32, device="cuda")
+    db = torch.zeros(32, dtype=torch.float32, device="cuda")
+    nn.conv3d_bwd_weight(_dev(xb), 32, _dev(gb), shape, work, dw, db)
+    torch.cuda.synchronize()
+    xq = bf16_value(xb).reshape(128, 128, 128, 32)
+    gq = bf16_value(gb).reshape(128, 128, 128, 32)
+    ew, eb = _dw_db_bounds(xq, gq, dw.cpu().numpy().astype(np.float64), db.cpu().numpy().astype(np.float64),
+                           taps=(0, 8, 13, 18, 26))
+    print(f"dw {ew:.3f}, db {eb:.3f} of their bounds", flush=True)
+    assert ew <= 1.0 and eb <= 1.0
+
+
 def test_relu_grad_mse_and_adamw():
     _case("relu gradient, mse, adamw")
     import torch
@@ -176,12 +245,10 @@ def test_relu_grad_mse_and_adamw():
     dyb = bf16_bits(rng.normal(size=(V, 32)))
     yb = bf16_bits(rng.normal(size=(V, 32)))
     g = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
-    gcf = torch.zeros((32, V), dtype=torch.int16, device="cuda")
-    nn.relu_grad(_dev(dyb), _dev(yb), V, g, gcf)
+    nn.relu_grad(_dev(dyb), _dev(yb), V, g)
     torch.cuda.synchronize()
     want = np.where(bf16_value(yb) > 0, bf16_value(dyb), 0.0)
     assert np.array_equal(bf16_value(g.cpu().numpy()), want)
-    assert np.array_equal(bf16_value(gcf.cpu().numpy()), want.T)
     pred = rng.normal(size=V).astype(np.float32)
     tgt = rng.normal(size=V).astype(np.float32)
     part = torch.zeros(256, dtype=torch.float32, device="cuda")
