@@ -69,6 +69,68 @@ int art_chem_step(long long ncell, const double *n_H, const double *rho, const f
                   const float *Heat, double *x_HI, double *u, double dt, const art_chem_params *p,
                   double *dt_chem, int *nsub, void *hip_stream);
 
+/*
+ * One radiative step coupled to the chemistry (Appendix D: the transfer
+ * equation is static, so the diffuse radiation field and the rate and energy
+ * equations are iterated until n_e and u converge in every cell).  The
+ * fields of the diffuse recombination radiation follow from the chemical
+ * state (Sect. 2.2): per bin b, kappa_b = sigma_b n_HI and the source
+ * function S_b = src_coef_b dalpha(T) n_e n_HII / n_HI (the rectangular
+ * recombination spectrum: src_coef = h nu_0 / (4 pi sigma dnu_th) in the
+ * paper's units), dalpha = alpha_A - alpha_B a table on the chemistry's
+ * log10 T grid, n_HI floored at x_floor n_H in both (a fully ionised cell
+ * then absorbs next to nothing and emits dalpha n_e n_HII per unit volume,
+ * the limit of the formal solution); cells with n_H <= 0 have kappa = S = 0.
+ * The rates are Gamma = sum_b gamma_w_b (J_in_b + S_b) and Heat =
+ * sum_b heat_in_b J_in_b + heat_src_b S_b (eqs gamma_diff, heat_diff; with
+ * gamma_w_b src_coef_b = 1 the S part of Gamma is the on-the-spot term
+ * dalpha n_e n_HII / n_HI).
+ */
+typedef struct {
+    int nbins;               /* 1..ART_MAX_BINS */
+    const float *sigma;      /* host [nbins]: kappa_b = sigma_b n_HI (per unit length), finite, >= 0 */
+    const float *src_coef;   /* host [nbins]: source-function coefficient, finite, >= 0 */
+    const double *dalpha;    /* device [nT] (the chemistry's grid): alpha_A - alpha_B */
+    const float *gamma_w;    /* host [nbins] or NULL (all 1) */
+    const float *heat_in;    /* host [nbins] or NULL (all 0) */
+    const float *heat_src;   /* host [nbins] or NULL (all 0) */
+    int nside;               /* HEALPix resolution of the sweeps, >= 1 */
+    double x_floor;          /* in (0, 1] */
+    int max_iter;            /* transfer-chemistry iterations, >= 1 */
+} art_rt_chem_params;
+
+typedef struct {
+    int iterations;          /* iterations run */
+    int converged;           /* 1: the last iteration met the tolerance in every cell */
+    double dt_chem_min;      /* minimum chemical timestep at the final state (+inf if none):
+                                the next radiative step is F times it (the paper: F = 1-10) */
+} art_rt_chem_result;
+
+/* Bytes of workspace art_rt_chem_step needs on this mesh with nbins bins
+ * (-1 for a NULL mesh or a bad bin count).  Host only. */
+long long art_rt_chem_workspace(const art_mesh *mesh, int nbins);
+
+/*
+ * Advance every cell of the mesh by the radiative step dt.  Iteration i
+ * (1 .. max_iter) loads the fields built from the state of iteration i - 1
+ * (iteration 0: x_HI, u as given) into the mesh (art_set_fields, with the
+ * heating weights), sweeps (art_sweep at nside, I_bc = 0), and advances the
+ * given state over dt with those rates (art_chem_step with cp); it stops when
+ * every cell with n_H > 0 has |n_e^(i) - n_e^(i-1)| <= eps n_e^(i) and
+ * |u^(i) - u^(i-1)| <= eps u^(i) (eps = cp->eps).  Then x_HI and u hold the
+ * last iteration's state.  n_H, rho, x_HI, u: device double [cells] (x
+ * fastest); Gamma, Heat: device float [cells] or NULL, the last iteration's
+ * rates.  work: device buffer of work_bytes >= art_rt_chem_workspace().
+ * res: host, filled on success.  The call blocks the host: after each
+ * iteration it waits for the stream to learn whether every cell converged.
+ * It replaces the mesh's fields and heating weights.  ART_E_INVAL for a bad
+ * argument (before any GPU work), or the code of the failing step.
+ */
+int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
+                     const double *n_H, const double *rho, double *x_HI, double *u, double dt,
+                     void *work, long long work_bytes, float *Gamma, float *Heat,
+                     art_rt_chem_result *res, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,7 +39,7 @@ SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_
 # include/art_point.h: rates from point sources
 PT_EXPORTS = ("art_point_sources", "art_point_sources_noalloc")
 # include/art_chem.h: chemistry and energy update of a radiative step
-CHEM_EXPORTS = ("art_chem_step",)
+CHEM_EXPORTS = ("art_chem_step", "art_rt_chem_workspace", "art_rt_chem_step")
 # include/art_diag.h: measurements behind design decisions
 DIAG_EXPORTS = ("art_diag_release_cost",)
 
@@ -68,6 +68,18 @@ class ChemParams(ctypes.Structure):
                 ("cool_II", ctypes.c_void_p), ("T_per_u", ctypes.c_double), ("eps", ctypes.c_double),
                 ("eps_e", ctypes.c_double), ("eps_HI", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_sub", ctypes.c_int)]
+
+
+class RtChemParams(ctypes.Structure):
+    """art_rt_chem_params (include/art_chem.h): host per-bin arrays, device dalpha."""
+    _fields_ = [("nbins", ctypes.c_int), ("sigma", ctypes.c_void_p), ("src_coef", ctypes.c_void_p),
+                ("dalpha", ctypes.c_void_p), ("gamma_w", ctypes.c_void_p), ("heat_in", ctypes.c_void_p),
+                ("heat_src", ctypes.c_void_p), ("nside", ctypes.c_int), ("x_floor", ctypes.c_double),
+                ("max_iter", ctypes.c_int)]
+
+
+class RtChemResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("dt_chem_min", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -154,9 +166,14 @@ def load(path: str = LIB_PATH):
     L.art_point_sources_noalloc.argtypes = [vp, i, vp, vp, vp, vp, vp, vp, vp, vp]
     L.art_chem_step.argtypes = [ctypes.c_longlong, vp, vp, vp, vp, vp, vp, d,
                                 ctypes.POINTER(ChemParams), vp, vp, vp]
+    L.art_rt_chem_workspace.argtypes = [vp, i]
+    L.art_rt_chem_workspace.restype = ctypes.c_longlong
+    L.art_rt_chem_step.argtypes = [vp, ctypes.POINTER(RtChemParams), ctypes.POINTER(ChemParams), vp, vp,
+                                   vp, vp, d, vp, ctypes.c_longlong, vp, vp, ctypes.POINTER(RtChemResult),
+                                   vp]
     L.art_diag_release_cost.argtypes = [i, i, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS + CHEM_EXPORTS + DIAG_EXPORTS:
-        if name != "art_last_error":
+        if name not in ("art_last_error", "art_rt_chem_workspace"):
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -535,3 +552,40 @@ class nn:
     def ood_count(x, V, lo, hi, count, stream=None):
         _check(load().art_nn_ood_count(_ptr(x), V, nn._f3(lo), nn._f3(hi), _ptr(count),
                                        _stream_ptr(stream)))
+
+
+def _farr(vals, nb):
+    return None if vals is None else (ctypes.c_float * nb)(*[float(v) for v in vals])
+
+
+def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, src_coef, dalpha,
+                 nside=1, gamma_w=None, heat_in=None, heat_src=None, x_floor=1e-6, max_iter=100,
+                 T_per_u=1.0, eps=1e-3, eps_e=0.2, eps_HI=0.002, chem_max_iter=100, max_sub=100000,
+                 Gamma=None, Heat=None, work=None, stream=None):
+    """art_rt_chem_step: one radiative step of `mesh` coupled to the chemistry.
+    n_H, rho, x_HI, u: float64 device tensors of the mesh's cells (x_HI, u
+    updated in place); tables: float64 device tensors alpha, k_ci, cool_I,
+    cool_II; dalpha: float64 device tensor on the same grid; sigma, src_coef
+    (and the optional weights): per-bin sequences.  Returns dict iterations,
+    converged, dt_chem_min."""
+    import torch
+    L = load()
+    nb = len(sigma)
+    if work is None:
+        nbytes = L.art_rt_chem_workspace(mesh._h, nb)
+        if nbytes < 0:
+            raise ValueError("rt_chem_step: bad bin count")
+        work = torch.empty(int(nbytes), dtype=torch.uint8, device=n_H.device)
+    nT = int(tables["alpha"].numel())
+    cp = ChemParams(nT, float(logT_min), float(dlogT), *[_ptr(tables[k]) for k in
+                    ("alpha", "k_ci", "cool_I", "cool_II")], float(T_per_u), float(eps), float(eps_e),
+                    float(eps_HI), int(chem_max_iter), int(max_sub))
+    arrs = [_farr(sigma, nb), _farr(src_coef, nb), _farr(gamma_w, nb), _farr(heat_in, nb), _farr(heat_src, nb)]
+    cv = [ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs]
+    rp = RtChemParams(nb, cv[0], cv[1], _ptr(dalpha), cv[2], cv[3], cv[4], int(nside), float(x_floor),
+                      int(max_iter))
+    res = RtChemResult()
+    _check(L.art_rt_chem_step(mesh._h, ctypes.byref(rp), ctypes.byref(cp), _ptr(n_H), _ptr(rho), _ptr(x_HI),
+                              _ptr(u), float(dt), _ptr(work), int(work.numel()), _ptr(Gamma), _ptr(Heat),
+                              ctypes.byref(res), _stream_ptr(stream)))
+    return dict(iterations=res.iterations, converged=bool(res.converged), dt_chem_min=res.dt_chem_min)

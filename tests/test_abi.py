@@ -79,6 +79,37 @@ def test_chem_argument_checks_without_gpu():
     assert L.art_chem_step(4, p, p, p, p, p, p, 1.0, None, None, None, None) == -1
 
 
+def test_rt_chem_argument_checks_without_gpu():
+    """The coupled step rejects bad parameters and a short workspace before any
+    device work; the workspace size follows the mesh and the bin count."""
+    import numpy as np
+    from paper_1410_0763_amd import art
+    L = art.load()
+    p = ctypes.c_void_p(1)
+    h = ctypes.c_void_p()
+    assert L.art_create_mesh(4, 5, 6, 1.0, ctypes.byref(h)) == 0
+    w1, w2 = L.art_rt_chem_workspace(h, 1), L.art_rt_chem_workspace(h, 2)
+    assert w1 > 120 * (8 * 5 + 4 * 4) and w2 - w1 >= 2 * 120 * 4
+    assert L.art_rt_chem_workspace(h, 0) == -1 and L.art_rt_chem_workspace(None, 1) == -1
+    cp = art.ChemParams(61, 1.0, 0.1, p, p, p, p, 1.0, 1e-3, 0.2, 0.002, 100, 1000)
+    one = (ctypes.c_float * 1)(1.0)
+    neg = (ctypes.c_float * 1)(-1.0)
+    res = art.RtChemResult()
+
+    def call(nb=1, sig=one, dal=p, nside=1, xf=1e-6, mi=10, dt=1.0, wb=w1, cpp=cp):
+        rp = art.RtChemParams(nb, ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(one, ctypes.c_void_p), dal,
+                              None, None, None, nside, xf, mi)
+        return L.art_rt_chem_step(h, ctypes.byref(rp), ctypes.byref(cpp), p, p, p, p, dt, p, wb, None, None,
+                                  ctypes.byref(res), None)
+    assert call(nb=0) == -1 and call(nb=5) == -1
+    assert call(sig=neg) == -1 and call(dal=None) == -1 and call(nside=0) == -1
+    assert call(xf=0.0) == -1 and call(xf=1.5) == -1 and call(mi=0) == -1
+    assert call(dt=-1.0) == -1 and call(dt=float("nan")) == -1
+    assert call(wb=w1 - 1) == -1 and b"workspace" in L.art_last_error()
+    assert call(cpp=art.ChemParams(1, 1.0, 0.1, p, p, p, p, 1.0, 1e-3, 0.2, 0.002, 100, 1000)) == -1
+    assert L.art_destroy_mesh(h) == 0
+
+
 def test_point_argument_checks_without_gpu():
     """Sources outside the box, negative or non-finite photon rates and calls
     before set_fields are rejected before any device work."""

@@ -1,0 +1,137 @@
+"""One radiative step coupled to the chemistry (art_rt_chem_step; Appendix D
+iteration, Sect. 2.2 fields) against the FP64 oracle (oracle/rtchem.py):
+every cell after 1, 2 and 3 forced iterations and after convergence, the
+iteration counts, the last iteration's rates; the thick-interior case-B
+balance; a 64^3 step for timing, bounds and bitwise repeatability."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import chem as C
+from oracle import rtchem as RC
+
+pytestmark = pytest.mark.gpu
+
+LT0, LT1, NT = 1.0, 9.0, 81
+
+
+def _tables():
+    T = 10.0 ** np.linspace(LT0, LT1, NT)
+    alpha = 2.0 * (T / 1e4) ** -0.7
+    return dict(alpha=alpha, k_ci=0.5 * np.exp(-1.6e5 / T), cool_I=3e-2 * np.exp(-1.2e5 / T),
+                cool_II=1e-4 * (T / 1e4) ** 0.5), 0.38 * alpha
+
+
+def _state(shape, seed):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    nH = rng.lognormal(0.0, 0.7, n)
+    nH[:2] = 0.0                                          # empty cells stay as they are
+    x = rng.uniform(0.05, 0.95, n)
+    u = 10.0 ** rng.uniform(1.5, 3.0, n)
+    return nH, nH * 1.2, x, u
+
+
+def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter):
+    import torch
+    from paper_1410_0763_amd import art
+    d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()
+    nz, ny, nx = shape
+    tables = {k: d(v) for k, v in tb.items()}
+    xg, ug = d(x), d(u)
+    G = torch.zeros(len(nH), dtype=torch.float32, device="cuda")
+    H = torch.zeros_like(G)
+    with art.Mesh(nx, ny, nz) as mesh:
+        r = art.rt_chem_step(mesh, d(nH), d(rho), xg, ug, dt, tables, LT0, (LT1 - LT0) / (NT - 1),
+                             rt["sigma"], rt["src_coef"], d(dal), nside=rt["nside"], gamma_w=rt["gamma_w"],
+                             heat_in=rt["heat_in"], heat_src=rt["heat_src"], x_floor=rt["x_floor"],
+                             max_iter=max_iter, T_per_u=T_per_u, Gamma=G, Heat=H)
+        torch.cuda.synchronize()
+    return r, xg.cpu().numpy(), ug.cpu().numpy(), G.cpu().numpy().astype(np.float64), \
+        H.cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def _case(nbins):
+    tb, dal = _tables()
+    cp = C.default_params(nT=NT, logT_min=LT0, logT_max=LT1, **tb)
+    cp.update(T_per_u=10.0)
+    rt = RC.default_rt_params(nbins=nbins, nT=NT, dalpha=dal, sigma=[2.0, 0.6][:nbins],
+                              src_coef=[1.0, 2.0][:nbins], gamma_w=[1.0, 0.5][:nbins],
+                              heat_in=[3.0, 1.0][:nbins], heat_src=[1.0, 0.5][:nbins], nside=2)
+    return tb, dal, cp, rt
+
+
+# The sweep meets its FP64 reference within 1e-5 (relative, per cell); the
+# fields are rounded to float32 (6e-8).  The chemistry's response to a rate
+# error is at most proportional (d ln x / d ln Gamma and d ln u / d ln Heat
+# within [-1, 1] for the backward-difference and implicit energy updates),
+# and three iterations pass it on at most three times: 1e-4 leaves a factor
+# of three over 3e-5.
+TOL = 1e-4
+
+
+@pytest.mark.parametrize("nbins,max_iter,dt", [(1, 1, 0.3), (1, 2, 0.3), (1, 3, 0.3), (2, 2, 0.3),
+                                               (1, 100, 0.3), (2, 100, 0.05)])
+def test_coupled_step_matches_oracle(nbins, max_iter, dt):
+    shape = (5, 6, 8)
+    print(f"\n== case coupled step {shape} bins {nbins} max_iter {max_iter} dt {dt}", flush=True)
+    tb, dal, cp, rt = _case(nbins)
+    nH, rho, x0, u0 = _state(shape, 40 + nbins)
+    ref = RC.step(shape, 1.0, nH, rho, x0, u0, dt, rt, cp, max_iter)
+    r, xg, ug, G, H = _run(shape, nH, rho, x0, u0, dt, tb, dal, rt, 10.0, max_iter)
+    ex, eu = _rel(xg, ref["x"]), _rel(ug, ref["u"])
+    sG = np.maximum(np.abs(ref["Gamma"]), 1e-6 * np.abs(ref["Gamma"]).max())
+    sH = np.maximum(np.abs(ref["Heat"]), 1e-6 * np.abs(ref["Heat"]).max())
+    eG, eH = np.max(np.abs(G - ref["Gamma"]) / sG), np.max(np.abs(H - ref["Heat"]) / sH)
+    print(f"iterations {r['iterations']} (oracle {ref['iterations']}), converged {r['converged']}; "
+          f"x_HI {ex.max():.2e}, u {eu.max():.2e}, Gamma {eG:.2e}, Heat {eH:.2e}; dt_chem_min "
+          f"{r['dt_chem_min']:.6e} (oracle {ref['dt_chem_min']:.6e})", flush=True)
+    assert r["iterations"] == ref["iterations"] and r["converged"] == ref["converged"]
+    assert ex.max() <= TOL and eu.max() <= TOL
+    assert eG <= 1e-5 and eH <= 1e-5
+    assert math.isfinite(r["dt_chem_min"]) and abs(r["dt_chem_min"] / ref["dt_chem_min"] - 1) <= 1e-3
+    assert np.array_equal(xg[:2], x0[:2]) and np.array_equal(ug[:2], u0[:2])
+
+
+def test_thick_interior_reaches_the_case_b_balance():
+    """The oracle's physical pin on the GPU: uniform thick medium, constant
+    alpha_A, dalpha, k_ci; the centre cell converges to
+    alpha_B / (alpha_B + k_ci)."""
+    print("\n== case coupled step, thick interior, case-B balance", flush=True)
+    a, da, k = 1.0, 0.4, 0.25
+    shape = (5, 5, 5)
+    n = 125
+    tb = dict(alpha=np.full(NT, a), k_ci=np.full(NT, k), cool_I=np.zeros(NT), cool_II=np.zeros(NT))
+    rt = RC.default_rt_params(sigma=[400.0], dalpha=np.full(NT, da), nside=1)
+    nH = np.ones(n)
+    r, xg, ug, _, _ = _run(shape, nH, nH, np.full(n, 0.9), np.full(n, 100.0), 400.0, tb, rt["dalpha"],
+                           rt, 1.0, 200)
+    xb = (a - da) / (a - da + k)
+    print(f"iterations {r['iterations']}, centre x_HI {xg[62]:.6f}, case B {xb:.6f}, case A "
+          f"{a / (a + k):.6f}", flush=True)
+    assert r["converged"]
+    assert abs(xg[62] - xb) <= 3e-3 * max(xb, 1 - xb)
+
+
+def test_coupled_step_64_cubed():
+    """64^3, Nside 2: converges, stays in bounds, and repeats bit for bit."""
+    print("\n== case coupled step 64^3", flush=True)
+    import time
+    tb, dal, cp, rt = _case(1)
+    shape = (64, 64, 64)
+    nH, rho, x0, u0 = _state(shape, 77)
+    t0 = time.perf_counter()
+    r1, x1, u1, _, _ = _run(shape, nH, rho, x0, u0, 0.3, tb, dal, rt, 10.0, 100)
+    t1 = time.perf_counter()
+    r2, x2, u2, _, _ = _run(shape, nH, rho, x0, u0, 0.3, tb, dal, rt, 10.0, 100)
+    print(f"iterations {r1['iterations']}, converged {r1['converged']}, {(t1 - t0) * 1e3:.1f} ms "
+          f"(first call, with setup), dt_chem_min {r1['dt_chem_min']:.4e}", flush=True)
+    assert r1["converged"] and r1 == r2
+    assert np.array_equal(x1, x2) and np.array_equal(u1, u2)
+    floor = 10.0 ** LT0 / 10.0
+    assert np.all((x1 >= 0) & (x1 <= 1)) and np.all(u1 >= floor)
