@@ -24,6 +24,7 @@ and the CPU share are reported with it.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -575,6 +576,31 @@ def bench_rtchem(steps=3, cpu=True):
     print(json.dumps(rec), flush=True)
 
 
+class Phases:
+    """roctx ranges around the benchmark's phases (setup, warm-up, timed
+    sweeps, CPU baseline), visible with rocprofv3 --marker-trace; a no-op
+    where the roctx library is absent."""
+
+    def __init__(self):
+        self._lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so"):
+            try:
+                self._lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        if self._lib is not None:
+            self._lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+
+    def push(self, name):
+        if self._lib is not None:
+            self._lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self._lib is not None:
+            self._lib.roctxRangePop()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,19 +663,26 @@ def main():
     if args.rtchem:
         bench_rtchem(steps=args.steps, cpu=not args.no_cpu_baseline)
         return
+    ph = Phases()
+    ph.push("setup: medium, mesh, fields")
     m = media.plain_256()
     nb, nz, ny, nx = m.kappa.shape
     mesh = art.Mesh(nx, ny, nz, m.cell_size)
     mesh.set_fields(torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
     out = mesh.alloc_outputs(m.nside)
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ph.pop()
 
+    ph.push("warm-up sweeps")
     for _ in range(args.warmup):
         mesh.sweep(m.nside, gamma_w=m.gamma_w, out=out)
     torch.cuda.synchronize()
+    ph.pop()
 
     march_ms, sweep_ms, segs = [], [], []
     torch.cuda.synchronize()
+    ph.push("timed sweeps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         mesh.sweep(m.nside, gamma_w=m.gamma_w, out=out)
@@ -659,6 +692,7 @@ def main():
         segs.append(st["segments"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ph.pop()
 
     seg_bins = segs[-1] * nb
     ms_per_step = 1e3 * wall / args.steps
@@ -705,7 +739,9 @@ def main():
     }
     mesh.close()
     if not args.no_cpu_baseline:
+        ph.push("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(m)
+        ph.pop()
     print(json.dumps(rec), flush=True)
 
 

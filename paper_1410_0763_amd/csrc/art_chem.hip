@@ -80,6 +80,9 @@ __device__ double u_new(const ChemArgs &a, double u0, double h, double H, double
     if (resid(lo) >= 0.0) return lo;
     for (int k = 0; k < 64; ++k) {
         const double mid = 0.5 * (lo + hi);
+        // lo and hi adjacent (or equal): every further halving leaves
+        // 0.5 (lo + hi) where it is, so stopping returns the same value
+        if (mid == lo || mid == hi) break;
         if (resid(mid) >= 0.0) hi = mid; else lo = mid;
     }
     return 0.5 * (lo + hi);
