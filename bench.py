@@ -576,6 +576,42 @@ def bench_rtchem(steps=3, cpu=True):
     print(json.dumps(rec), flush=True)
 
 
+def bench_bwd_weight(reps=20):
+    """Weight and bias gradients of one 32 -> 32 and one 16 -> 32 layer at
+    128^3 (random bf16 operands): HIP events around art_conv3d_bwd_weight
+    (products and the fixed-order partial sums), best of 5 runs of reps calls."""
+    import numpy as np
+    import torch
+    from paper_1410_0763_amd.art import nn
+    shape = (128, 128, 128)
+    V = 128 ** 3
+    rng = np.random.default_rng(1)
+    g = torch.from_numpy(rng.integers(-20000, 20000, size=(V, 32), dtype=np.int16)).cuda()
+    x32 = torch.from_numpy(rng.integers(-20000, 20000, size=(V, 32), dtype=np.int16)).cuda()
+    rows = []
+    for cin in (32, 16):
+        x = x32[:, :cin].contiguous()
+        work = torch.zeros(nn.bwd_weight_workspace(cin, shape), dtype=torch.float32, device="cuda")
+        dw = torch.zeros((27, cin, 32), dtype=torch.float32, device="cuda")
+        db = torch.zeros(32, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            nn.conv3d_bwd_weight(x, cin, g, shape, work, dw, db)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = 1e30
+        for _ in range(5):
+            e0.record()
+            for _ in range(reps):
+                nn.conv3d_bwd_weight(x, cin, g, shape, work, dw, db)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+        flop = 2.0 * 27 * 32 * 32 * V          # the 16-channel layer fills half of each tile
+        rows.append({"cin": cin, "ms": best, "tflops_of_32x32_work": flop / (best / 1e3) / 1e12,
+                     "frac": flop / (best / 1e3) / 1e12 / 2500.0})
+    print(json.dumps({"metric": "ms per weight+bias gradient of a conv3d layer (128^3, 27 taps, 32 out "
+                                "channels)", "rows": rows, "peak_tflops": 2500.0}), flush=True)
+
+
 class Phases:
     """roctx ranges around the benchmark's phases (setup, warm-up, timed
     sweeps, CPU baseline), visible with rocprofv3 --marker-trace; a no-op
@@ -625,6 +661,8 @@ def main():
                     help="measure the cost of agent-scope release/acquire per workgroup")
     ap.add_argument("--chem", action="store_true",
                     help="measure the chemistry and energy update (128^3) instead of the 256^3 sweep")
+    ap.add_argument("--bwd-weight", action="store_true",
+                    help="time the surrogate's weight-gradient kernel on one 128^3 layer")
     ap.add_argument("--rtchem", action="store_true",
                     help="measure a radiative step coupled to the chemistry (128^3, Nside 2)")
     args = ap.parse_args()
@@ -662,6 +700,9 @@ def main():
         return
     if args.rtchem:
         bench_rtchem(steps=args.steps, cpu=not args.no_cpu_baseline)
+        return
+    if args.bwd_weight:
+        bench_bwd_weight()
         return
     ph = Phases()
     ph.push("setup: medium, mesh, fields")

@@ -28,11 +28,14 @@ extern "C" {
 
 /* Convolution of x (cin = 16 or 32 channels) with 32 output channels.
  * w_k: bf16 [27][32][cin] (made by art_nn_prep_weights); bias: float32 [32]
- * or NULL; relu: apply max(0, .) after the bias.  Outputs (either may be
- * NULL): y bf16 [V][32], y0 float32 [V] = channel 0 of the output.
- * W must be a multiple of 32.  ART_E_INVAL on bad sizes or null x/w_k. */
+ * or NULL; relu: apply max(0, .) after the bias.  mask: bf16 [V][32] or
+ * NULL: y is set to 0 wherever mask <= 0 (the ReLU gradient of the layer
+ * whose output mask is, fused into the input-gradient convolution).
+ * Outputs (either may be NULL): y bf16 [V][32], y0 float32 [V] = channel 0
+ * of the output (never masked).  W must be a multiple of 32.  ART_E_INVAL on
+ * bad sizes or null x/w_k. */
 int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, int D, int H,
-                   int W, int relu, void *y, float *y0, void *hip_stream);
+                   int W, int relu, const void *mask, void *y, float *y0, void *hip_stream);
 
 /* Weight and bias gradients of one layer:
  * dw[tap][ci][co] = sum_v x[v + offset(tap)][ci] g[v][co] (zero padding) and

@@ -131,7 +131,7 @@ def load(path: str = LIB_PATH):
     L.art_graph_destroy.argtypes = [vp]
     L.art_last_error.restype = ctypes.c_char_p
     fp = ctypes.POINTER(ctypes.c_float)
-    L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
+    L.art_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp, vp]
     L.art_conv3d_bwd_weight.argtypes = [vp, i, vp, i, i, i, vp, ctypes.c_longlong, vp, vp, vp]
     L.art_conv3d_bwd_weight_workspace.argtypes = [i, i, i, i]
     L.art_conv3d_bwd_weight_workspace.restype = ctypes.c_longlong
@@ -489,10 +489,10 @@ class nn:
         return (ctypes.c_float * 3)(*[float(v) for v in vals])
 
     @staticmethod
-    def conv3d_fwd(x, cin, w_k, bias, shape, relu, y=None, y0=None, stream=None):
+    def conv3d_fwd(x, cin, w_k, bias, shape, relu, y=None, y0=None, mask=None, stream=None):
         D, H, W = shape
         _check(load().art_conv3d_fwd(_ptr(x), cin, _ptr(w_k), _ptr(bias), D, H, W, int(relu),
-                                     _ptr(y), _ptr(y0), _stream_ptr(stream)))
+                                     _ptr(mask), _ptr(y), _ptr(y0), _stream_ptr(stream)))
 
     @staticmethod
     def bwd_weight_workspace(cin, shape):

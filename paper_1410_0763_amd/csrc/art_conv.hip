@@ -75,6 +75,7 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
                                                        const uint16_t *__restrict__ w,
                                                        const float *__restrict__ bias, int D,
                                                        int H, int W, int relu,
+                                                       const uint16_t *__restrict__ mask,
                                                        uint16_t *__restrict__ y,
                                                        float *__restrict__ y0)
 {
@@ -154,6 +155,19 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
                         const int c = c0 + 8 * h + 2 * e;
                         p[h][e] = (unsigned)f2bf((*tile)[row][c]) | ((unsigned)f2bf((*tile)[row][c + 1]) << 16);
                     }
+                if (mask) {                                    // keep where mask > 0
+                    const u32x4 *mk = reinterpret_cast<const u32x4 *>(mask + (v0 + row) * 32 + c0);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const u32x4 mm = mk[h];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const unsigned lo = bf2f((uint16_t)(mm[e] & 0xffffu)) > 0.0f ? 0x0000ffffu : 0u;
+                            const unsigned hi = bf2f((uint16_t)(mm[e] >> 16)) > 0.0f ? 0xffff0000u : 0u;
+                            p[h][e] &= lo | hi;
+                        }
+                    }
+                }
                 u32x4 *dst = reinterpret_cast<u32x4 *>(y + (v0 + row) * 32 + c0);
                 dst[0] = p[0];
                 dst[1] = p[1];
@@ -644,7 +658,7 @@ __global__ void art_fill_u32_kernel_entry(unsigned int *p) { *p = 0u; }
 extern "C" {
 
 int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, int D, int H,
-                   int W, int relu, void *y, float *y0, void *hip_stream)
+                   int W, int relu, const void *mask, void *y, float *y0, void *hip_stream)
 {
     if (!x || !w_k) return art_set_error(ART_E_INVAL, "art_conv3d_fwd: null input or weights");
     if (cin != 16 && cin != 32) return art_set_error(ART_E_INVAL, "art_conv3d_fwd: cin must be 16 or 32");
@@ -669,10 +683,10 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
     }
     if (cin == 16)
         hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3((unsigned)tiles), dim3(512), conv_lds_bytes<16>(), st,
-                           xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
+                           xp, wp, bias, D, H, W, relu, (const uint16_t *)mask, (uint16_t *)y, y0);
     else
         hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3((unsigned)tiles), dim3(512), conv_lds_bytes<32>(), st,
-                           xp, wp, bias, D, H, W, relu, (uint16_t *)y, y0);
+                           xp, wp, bias, D, H, W, relu, (const uint16_t *)mask, (uint16_t *)y, y0);
     return launch_status("art_conv3d_fwd");
 }
 

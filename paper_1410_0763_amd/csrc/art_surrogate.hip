@@ -264,7 +264,7 @@ struct art_surrogate {
     float *w[NL] = {}, *b[NL] = {}, *mw[NL] = {}, *vw[NL] = {}, *mb[NL] = {}, *vb[NL] = {};
     float *dw[NL] = {}, *db[NL] = {};
     uint16_t *w_fwd[NL] = {}, *w_bwd[NL] = {};
-    uint16_t *acts[NL - 1] = {}, *dy[2] = {}, *g = nullptr, *x = nullptr;
+    uint16_t *acts[NL - 1] = {}, *dy[2] = {}, *x = nullptr;
     float *pred = nullptr, *work = nullptr, *mpart = nullptr,
           *wpart = nullptr, *loss = nullptr;
     float *Jc = nullptr, *Jexc = nullptr, *Jinc = nullptr, *Jf = nullptr, *Jinf = nullptr;
@@ -309,7 +309,7 @@ int forward(art_surrogate *s, const void *x, hipStream_t st)
     RCCHK(prep(s, st));
     for (int l = 0; l < NL; ++l) {
         const void *xin = l == 0 ? x : s->acts[l - 1];
-        RCCHK(art_conv3d_fwd(xin, CIN[l], s->w_fwd[l], s->b[l], s->D, s->H, s->W, RELU[l],
+        RCCHK(art_conv3d_fwd(xin, CIN[l], s->w_fwd[l], s->b[l], s->D, s->H, s->W, RELU[l], nullptr,
                              l < NL - 1 ? s->acts[l] : nullptr, l == NL - 1 ? s->pred : nullptr, st));
     }
     return ART_OK;
@@ -365,7 +365,7 @@ int art_surrogate_create(int nx, int ny, int nz, unsigned long long seed, art_su
     }
     for (int l = 0; l < NL - 1; ++l) A(&s->acts[l], V * 32);
     A(&s->dy[0], V * 32); A(&s->dy[1], V * 32);
-    A(&s->g, V * 32); A(&s->x, V * 16);
+    A(&s->x, V * 16);
     A(&s->pred, V); A(&s->Jc, V); A(&s->Jexc, V); A(&s->Jinc, V); A(&s->Jf, V); A(&s->Jinf, V);
     A(&s->work, (size_t)s->nwork);
     A(&s->mpart, 256); A(&s->wpart, 257); A(&s->loss, 1); A(&s->count, 1);
@@ -526,15 +526,17 @@ int art_surrogate_gradients(art_surrogate *s, const void *x, const float *target
     const int V = (int)s->V;
     RCCHK(forward(s, x, st));
     RCCHK(art_nn_mse(s->pred, target, weight, V, s->mpart, loss ? loss : s->loss, s->dy[0], st));
+    // dy[cur] holds the gradient at layer l's pre-activation output: the loss
+    // gradient for the last layer (no ReLU), else the input gradient of
+    // layer l + 1 with layer l's ReLU mask applied by the convolution itself
     int cur = 0;
     for (int l = NL - 1; l >= 0; --l) {
-        RCCHK(art_nn_relu_grad(s->dy[cur], l < NL - 1 ? s->acts[l] : nullptr, V, s->g, st));
         const void *xin = l == 0 ? x : s->acts[l - 1];
-        RCCHK(art_conv3d_bwd_weight(xin, CIN[l], s->g, s->D, s->H, s->W, s->work, s->nwork, s->dw[l],
-                                    s->db[l], st));
+        RCCHK(art_conv3d_bwd_weight(xin, CIN[l], s->dy[cur], s->D, s->H, s->W, s->work, s->nwork,
+                                    s->dw[l], s->db[l], st));
         if (l > 0) {
-            RCCHK(art_conv3d_fwd(s->g, 32, s->w_bwd[l], nullptr, s->D, s->H, s->W, 0, s->dy[1 - cur],
-                                 nullptr, st));
+            RCCHK(art_conv3d_fwd(s->dy[cur], 32, s->w_bwd[l], nullptr, s->D, s->H, s->W, 0, s->acts[l - 1],
+                                 s->dy[1 - cur], nullptr, st));
             cur = 1 - cur;
         }
     }

@@ -163,9 +163,9 @@ def test_nn_argument_checks_without_gpu():
     from paper_1410_0763_amd import art
     L = art.load()
     p = ctypes.c_void_p(1)
-    assert L.art_conv3d_fwd(None, 16, p, None, 4, 4, 32, 1, p, None, None) == -1
-    assert L.art_conv3d_fwd(p, 8, p, None, 4, 4, 32, 1, p, None, None) == -1
-    assert L.art_conv3d_fwd(p, 16, p, None, 4, 4, 48, 1, p, None, None) == -1
+    assert L.art_conv3d_fwd(None, 16, p, None, 4, 4, 32, 1, None, p, None, None) == -1
+    assert L.art_conv3d_fwd(p, 8, p, None, 4, 4, 32, 1, None, p, None, None) == -1
+    assert L.art_conv3d_fwd(p, 16, p, None, 4, 4, 48, 1, None, p, None, None) == -1
     assert b"multiple of 32" in L.art_last_error()
     assert L.art_conv3d_bwd_weight(p, 32, p, 4, 4, 24, p, 1 << 30, p, None, None) == -1
     assert b"multiple of 16" in L.art_last_error()

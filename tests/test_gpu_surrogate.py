@@ -87,7 +87,15 @@ def test_conv_gradients_match_reference():
         nn.conv3d_bwd_weight(xd, cin, g, shape, work, dw, db)
         dx = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
         nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dx)
+        # the ReLU gradient fused into the convolution: y where mask > 0 (mask
+        # with zeros, negatives and -0 among its values), else 0, bit for bit
+        mk = bf16_bits(np.where(rng.uniform(size=(V, 32)) < 0.2, 0.0, rng.normal(size=(V, 32))))
+        mk[::7, 3] = np.int16(-32768)                                  # -0.0
+        dxm = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+        nn.conv3d_fwd(g, 32, wbw, None, shape, 0, y=dxm, mask=_dev(mk))
         torch.cuda.synchronize()
+        keep = bf16_value(mk) > 0
+        assert np.array_equal(dxm.cpu().numpy(), np.where(keep, dx.cpu().numpy(), 0))
         wq = bf16_value(bf16_bits(w))
         rdx, rdw, rdb = R.conv3d_backward(bf16_value(xb), wq, bf16_value(gb))
         e_dw = _rel(dw.cpu().numpy(), rdw)
