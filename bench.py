@@ -612,6 +612,44 @@ def bench_bwd_weight(reps=20):
                                 "channels)", "rows": rows, "peak_tflops": 2500.0}), flush=True)
 
 
+def bench_conv_fwd(reps=20):
+    """Forward convolution of one 32 -> 32 and one 16 -> 32 layer at 128^3
+    (random bf16 input and weights, bias, ReLU): HIP events around
+    art_conv3d_fwd, best of 5 runs of reps calls."""
+    import numpy as np
+    import torch
+    from paper_1410_0763_amd.art import nn
+    shape = (128, 128, 128)
+    V = 128 ** 3
+    rng = np.random.default_rng(2)
+    x32 = torch.from_numpy(rng.integers(-20000, 20000, size=(V, 32), dtype=np.int16)).cuda()
+    y = torch.zeros((V, 32), dtype=torch.int16, device="cuda")
+    bias = torch.zeros(32, dtype=torch.float32, device="cuda")
+    rows = []
+    for cin in (32, 16):
+        x = x32[:, :cin].contiguous()
+        w = torch.from_numpy((rng.normal(size=(27, cin, 32)) * 0.05).astype(np.float32)).cuda()
+        wf = torch.zeros((27, 32, cin), dtype=torch.int16, device="cuda")
+        wb = torch.zeros((27, 32, 32), dtype=torch.int16, device="cuda")
+        nn.prep_weights(w, cin, wf, wb)
+        for _ in range(3):
+            nn.conv3d_fwd(x, cin, wf, bias, shape, 1, y=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = 1e30
+        for _ in range(5):
+            e0.record()
+            for _ in range(reps):
+                nn.conv3d_fwd(x, cin, wf, bias, shape, 1, y=y)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+        flop = 2.0 * 27 * cin * 32 * V
+        rows.append({"cin": cin, "ms": best, "tflops": flop / (best / 1e3) / 1e12,
+                     "frac": flop / (best / 1e3) / 1e12 / 2500.0})
+    print(json.dumps({"metric": "ms per forward conv3d layer (128^3, 27 taps, 32 out channels, bias, ReLU)",
+                      "rows": rows, "peak_tflops": 2500.0}), flush=True)
+
+
 class Phases:
     """roctx ranges around the benchmark's phases (setup, warm-up, timed
     sweeps, CPU baseline), visible with rocprofv3 --marker-trace; a no-op
@@ -661,6 +699,8 @@ def main():
                     help="measure the cost of agent-scope release/acquire per workgroup")
     ap.add_argument("--chem", action="store_true",
                     help="measure the chemistry and energy update (128^3) instead of the 256^3 sweep")
+    ap.add_argument("--conv-fwd", action="store_true",
+                    help="time the surrogate's forward convolution on one 128^3 layer")
     ap.add_argument("--bwd-weight", action="store_true",
                     help="time the surrogate's weight-gradient kernel on one 128^3 layer")
     ap.add_argument("--rtchem", action="store_true",
@@ -703,6 +743,9 @@ def main():
         return
     if args.bwd_weight:
         bench_bwd_weight()
+        return
+    if args.conv_fwd:
+        bench_conv_fwd()
         return
     ph = Phases()
     ph.push("setup: medium, mesh, fields")

@@ -71,7 +71,7 @@ constexpr int CONV_VS = 24;                                          // bf16 per
 template <int CIN> constexpr int conv_lds_bytes() { return (CONV_ROWS * CONV_COLS + 9 * 32) * CONV_VS * 2; }
 
 template <int CIN>
-__global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restrict__ x,
+__global__ __launch_bounds__(512, 6) void conv_fwd_kernel(const uint16_t *__restrict__ x,
                                                        const uint16_t *__restrict__ w,
                                                        const float *__restrict__ bias, int D,
                                                        int H, int W, int relu,
@@ -95,39 +95,66 @@ __global__ __launch_bounds__(512) void conv_fwd_kernel(const uint16_t *__restric
     f32x16 acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = f32x16{};
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int zz = zz0 + dz;
-        if (zz < 0 || zz >= D) continue;                       // uniform over the workgroup
-        for (int ks = 0; ks < CIN / 16; ++ks) {
-            __syncthreads();                                   // the previous stage is consumed
-            for (int c = threadIdx.x; c < CONV_ROWS * CONV_COLS * 2; c += 512) {
-                const int q = c & 1, vox = c >> 1, col = vox % CONV_COLS, row = vox / CONV_COLS;
-                const int yy = yb - 1 + row, xx = x0 - 1 + col;
-                const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-                const unsigned off =
-                    ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + 32 * ks + 16 * q) : NN_OOB;
-                *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
-            }
-            for (int c = threadIdx.x; c < 9 * 32 * 2; c += 512) {
-                const int q = c & 1, row = c >> 1;               // row = tap in dz * 32 + co
-                const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + 32 * ks + 16 * q);
-                *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
-            }
-            __syncthreads();
+    // Stages (dz, group ks of 16 input channels), planes outside the mesh
+    // skipped.  The input tile of the next stage is loaded into registers
+    // while the current one is multiplied, so that its latency overlaps the
+    // products.  A thread's 16-byte chunks c = tid + 512 j: chunk c is half q
+    // = bit 4 of c of voxel 16 (c >> 5) + (c & 15), so that 16 consecutive
+    // lanes write 16 different voxels (48 bytes apart: no two in one bank).
+    constexpr int KS = CIN / 16, NVOX = CONV_ROWS * CONV_COLS, NXC = (NVOX + 15) / 16 * 32;
+    auto stage_ok = [&](int sidx) { const int zz = zz0 + sidx / KS - 1; return zz >= 0 && zz < D; };
+    u32x4 xr[(NXC + 511) / 512];
+    auto xload = [&](int sidx) {
+        const int zz = zz0 + sidx / KS - 1, ks = sidx % KS;
 #pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                bf16x8 a[R + 2];
+        for (int j = 0; j < (NXC + 511) / 512; ++j) {
+            const int c = threadIdx.x + 512 * j;
+            const int q = (c >> 4) & 1, vox = ((c >> 5) << 4) | (c & 15);
+            const int col = vox % CONV_COLS, row = vox / CONV_COLS;
+            const int yy = yb - 1 + row, xx = x0 - 1 + col;
+            const bool ok = c < NXC && vox < NVOX && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const unsigned off =
+                ok ? (unsigned)((((long long)zz * H + yy) * W + xx) * CIN * 2 + 32 * ks + 16 * q) : NN_OOB;
+            xr[j] = __builtin_amdgcn_raw_buffer_load_b128(rX, off, 0, 0);
+        }
+    };
+    int sidx = 0;
+    while (!stage_ok(sidx)) ++sidx;                            // dz = 0 always is
+    xload(sidx);
+    for (; sidx < 3 * KS; ++sidx) {
+        if (!stage_ok(sidx)) continue;                         // uniform over the workgroup
+        const int dz = sidx / KS - 1, ks = sidx % KS;
+        __syncthreads();                                       // the previous stage is consumed
 #pragma unroll
-                for (int r = 0; r < R + 2; ++r)
-                    a[r] = *reinterpret_cast<const bf16x8 *>(sx + ((wave * R + r) * CONV_COLS + m + 1 + dx) * VS + 8 * kh);
+        for (int j = 0; j < (NXC + 511) / 512; ++j) {
+            const int c = threadIdx.x + 512 * j;
+            const int q = (c >> 4) & 1, vox = ((c >> 5) << 4) | (c & 15);
+            if (c < NXC && vox < NVOX) *reinterpret_cast<u32x4 *>(sx + vox * VS + q * 8) = xr[j];
+        }
+        for (int c = threadIdx.x; c < 9 * 32 * 2; c += 512) {
+            const int q = (c >> 4) & 1, row = ((c >> 5) << 4) | (c & 15);   // row = tap in dz * 32 + co
+            const unsigned off = (unsigned)((((dz + 1) * 9 * 32 + row) * CIN) * 2 + 32 * ks + 16 * q);
+            *reinterpret_cast<u32x4 *>(sw + row * VS + q * 8) = __builtin_amdgcn_raw_buffer_load_b128(rW, off, 0, 0);
+        }
+        __syncthreads();
+        {
+            int nx = sidx + 1;
+            while (nx < 3 * KS && !stage_ok(nx)) ++nx;
+            if (nx < 3 * KS) xload(nx);                        // in flight during the products
+        }
 #pragma unroll
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int tl = (dy + 1) * 3 + (dx + 1);
-                    const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(sw + (tl * 32 + m) * VS + 8 * kh);
+        for (int dx = -1; dx <= 1; ++dx) {
+            bf16x8 a[R + 2];
 #pragma unroll
-                    for (int q = 0; q < R; ++q)
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q + dy + 1], bw, acc[q], 0, 0, 0);
-                }
+            for (int r = 0; r < R + 2; ++r)
+                a[r] = *reinterpret_cast<const bf16x8 *>(sx + ((wave * R + r) * CONV_COLS + m + 1 + dx) * VS + 8 * kh);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int tl = (dy + 1) * 3 + (dx + 1);
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(sw + (tl * 32 + m) * VS + 8 * kh);
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q + dy + 1], bw, acc[q], 0, 0, 0);
             }
         }
     }
