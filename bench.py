@@ -261,7 +261,7 @@ def bench_batched(count=48, reps=5):
     print(json.dumps(rec), flush=True)
 
 
-def bench_surrogate(train_fields=64, steps=4800, lam=1.0, test_fields=8):
+def bench_surrogate(train_fields=512, steps=9600, lam=1.0, test_fields=64):
     """128^3, Nside 2 -> 16: time of coarse sweep + network inference against
     the fine sweep, held-out errors (the gate's relative L2 of J and the
     per-cell log error), and the conv layer's matrix-core rate.  Inputs are
@@ -693,8 +693,9 @@ def main():
                     help="measure the learned surrogate (128^3) instead of the 256^3 sweep")
     ap.add_argument("--point", action="store_true",
                     help="measure point-source RT (128^3, 16 sources) instead of the 256^3 sweep")
-    ap.add_argument("--sg-fields", type=int, default=64, help="training fields of --surrogate")
-    ap.add_argument("--sg-steps", type=int, default=4800, help="training steps of --surrogate")
+    ap.add_argument("--sg-fields", type=int, default=512, help="training fields of --surrogate")
+    ap.add_argument("--sg-steps", type=int, default=9600, help="training steps of --surrogate")
+    ap.add_argument("--sg-test", type=int, default=64, help="held-out fields of --surrogate")
     ap.add_argument("--release-cost", action="store_true",
                     help="measure the cost of agent-scope release/acquire per workgroup")
     ap.add_argument("--chem", action="store_true",
@@ -725,7 +726,7 @@ def main():
         bench_batched()
         return
     if args.surrogate:
-        bench_surrogate(train_fields=args.sg_fields, steps=args.sg_steps)
+        bench_surrogate(train_fields=args.sg_fields, steps=args.sg_steps, test_fields=args.sg_test)
         return
     if args.point:
         bench_point(steps=args.steps, cpu=not args.no_cpu_baseline)
