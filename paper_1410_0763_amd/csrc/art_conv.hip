@@ -653,14 +653,12 @@ template <int CIN, int S>
 int bw_launch_s(const BwPlan &p, const uint16_t *x, const uint16_t *g, int D, int H, int W, float *work,
                 hipStream_t st)
 {
-    static bool configured = false;
-    if (!configured) {
-        const hipError_t e = hipFuncSetAttribute((const void *)conv_bwdw_kernel<CIN, S>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, bw_lds_bytes<CIN>());
-        if (e != hipSuccess)
-            return art_set_error(ART_E_HIP, (std::string("art_conv3d_bwd_weight: ") + hipGetErrorString(e)).c_str());
-        configured = true;
-    }
+    // (a function-local static: initialised once, thread-safely)
+    static const hipError_t cfg = hipFuncSetAttribute((const void *)conv_bwdw_kernel<CIN, S>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      bw_lds_bytes<CIN>());
+    if (cfg != hipSuccess)
+        return art_set_error(ART_E_HIP, (std::string("art_conv3d_bwd_weight: ") + hipGetErrorString(cfg)).c_str());
     hipLaunchKernelGGL((conv_bwdw_kernel<CIN, S>), dim3(p.nwg), dim3(BW_THREADS), bw_lds_bytes<CIN>(), st, x, g, D,
                        H, W, p.ntx, p.planes, p.nwg, (int)(p.nwg % 8 == 0), work);
     return ART_OK;
@@ -697,17 +695,17 @@ int art_conv3d_fwd(const void *x, int cin, const void *w_k, const float *bias, i
     const long long tiles = (long long)D * ((H + 15) / 16) * (W / 32);
     const auto *xp = (const uint16_t *)x;
     const auto *wp = (const uint16_t *)w_k;
-    static bool configured = false;   // LDS above the 64 KiB default needs an opt-in
-    if (!configured) {
+    // the dynamic LDS opt-in, once (a function-local static initialises thread-safely)
+    static const hipError_t cfg = [] {
         hipError_t e = hipFuncSetAttribute((const void *)conv_fwd_kernel<16>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<16>());
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void *)conv_fwd_kernel<32>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, conv_lds_bytes<32>());
-        if (e != hipSuccess)
-            return art_set_error(ART_E_HIP, (std::string("art_conv3d_fwd: ") + hipGetErrorString(e)).c_str());
-        configured = true;
-    }
+        return e;
+    }();
+    if (cfg != hipSuccess)
+        return art_set_error(ART_E_HIP, (std::string("art_conv3d_fwd: ") + hipGetErrorString(cfg)).c_str());
     if (cin == 16)
         hipLaunchKernelGGL(conv_fwd_kernel<16>, dim3((unsigned)tiles), dim3(512), conv_lds_bytes<16>(), st,
                            xp, wp, bias, D, H, W, relu, (const uint16_t *)mask, (uint16_t *)y, y0);
