@@ -26,7 +26,10 @@ Readings (the paper gives the model, not the code):
 * R2 rates.  Gamma = sum_b g_b (J_in_b + S_b), Heat = sum_b (hin_b J_in_b +
   hsrc_b S_b) of the sweep (eqs gamma_diff and heat_diff, the frequency
   integrals folded into caller weights); g_b S_b is the on-the-spot term
-  dalpha n_e n_HII / n_HI of eq gamma_diff when g_b c_b = 1.
+  dalpha n_e n_HII / n_HI of eq gamma_diff when g_b c_b = 1.  Point sources,
+  if any, add their photon-conserving rates per absorber (Sect. 2.3,
+  Appendix A; `oracle.point`) for the same kappa, with the same floored
+  n_HI as the absorber density.
 * R3 iteration.  Iteration i (i = 1, 2, ...) builds the fields from the state
   of iteration i - 1 (iteration 0: the state at the start of the step),
   sweeps, and advances every cell from the start state over dt with those
@@ -103,6 +106,12 @@ def step(shape, h, nH, rho, x0, u0, dt, rp, cp, max_iter, nthreads=0):
                       nthreads=nthreads)
         G = out["Gamma"].reshape(-1)
         H = out["Heat"].reshape(-1)
+        if rp.get("src_pos") is not None and len(rp["src_pos"]):
+            n_abs = np.where(nH > 0.0, nH * np.maximum(x_prev, rp["x_floor"]), 0.0)
+            pt = O.point(kappa.reshape(nb, nz, ny, nx), n_abs.reshape(nz, ny, nx), rp["src_pos"],
+                         rp["src_Q"], rp.get("src_e"), h=h, nthreads=nthreads)
+            G = G + pt["Gamma"]
+            H = H + pt["Heat"]
         x_new, u_new, dtc, _ = C.step(nH, rho, G, H, x0.reshape(-1), u0.reshape(-1), dt, cp)
         conv = converged(nH, x_new, u_new, x_prev, u_prev, cp["eps"])
         x_prev, u_prev = x_new, u_new
@@ -115,8 +124,10 @@ def step(shape, h, nH, rho, x0, u0, dt, rp, cp, max_iter, nthreads=0):
 def default_rt_params(nbins=1, nT=61, **kw):
     """Radiation parameters: sigma 1, src_coef 1, dalpha all zero, weights
     g = 1 / src_coef (the on-the-spot balance of R2), no heating, Nside 1,
-    x_floor 1e-6."""
+    x_floor 1e-6, no point sources (src_pos (nsrc, 3) cell units, src_Q
+    (nsrc, nbins) photon rates, src_e (nbins,) or None)."""
     rp = dict(sigma=[1.0] * nbins, src_coef=[1.0] * nbins, dalpha=np.zeros(nT), gamma_w=[1.0] * nbins,
-              heat_in=[0.0] * nbins, heat_src=[0.0] * nbins, nside=1, x_floor=1e-6)
+              heat_in=[0.0] * nbins, heat_src=[0.0] * nbins, nside=1, x_floor=1e-6,
+              src_pos=None, src_Q=None, src_e=None)
     rp.update(kw)
     return rp

@@ -124,6 +124,27 @@ def test_heating_reaches_the_energy_equation():
     assert np.allclose(r["x"], x0, rtol=4e-16, atol=0)
 
 
+def test_point_source_in_a_thin_column_reaches_photoionisation_equilibrium():
+    """One source at the centre of the first cell of a thin 160-cell column,
+    no diffuse emission (dalpha = 0), constant alpha, no collisions: far from
+    the source the photon-conserving rate per HI atom is sigma Q / (4 pi r^2)
+    (Sect. 2.3), so after a long step x_HI solves alpha n_H (1 - x)^2 =
+    Gamma x there (to the shell rate's 2e-4 and the iteration tolerance)."""
+    N, a, sig = 160, 1.0, 1e-9
+    shape = (N, 1, 1)
+    nH = np.full(N, 1.0)
+    Q = 4.0 * np.pi * 60.0 ** 2 / sig                     # Gamma = 1 at r = 60
+    cp = C.default_params(alpha=_const(a))
+    rp = RC.default_rt_params(sigma=[sig], src_pos=[[0.5, 0.5, 0.5]], src_Q=[[Q]])
+    r = RC.step(shape, 1.0, nH, nH, np.full(N, 0.5), np.full(N, 100.0), 200.0, rp, cp, max_iter=20)
+    assert r["converged"]
+    for k in (30, 60, 150):
+        G = sig * Q / (4.0 * np.pi * k ** 2)
+        x_eq = ((2 * a + G) - np.sqrt((2 * a + G) ** 2 - 4 * a * a)) / (2 * a)
+        assert abs(r["x"][k] - x_eq) <= 3e-3 * max(x_eq, 1 - x_eq), (k, r["x"][k], x_eq)
+        assert abs(r["Gamma"][k] / G - 1) <= 3e-3
+
+
 def test_converged_state_is_a_fixed_point():
     """One more iteration from a converged state moves n_e and u by no more
     than the tolerance (the iteration contracts)."""
