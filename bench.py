@@ -533,7 +533,12 @@ def bench_rtchem(steps=3, cpu=True):
     mesh = art.Mesh(nx, ny, nz)
     mesh_ws = art.load().art_rt_chem_workspace(mesh._h, 1)
     work = torch.empty(mesh_ws, dtype=torch.uint8, device="cuda")
-    kw = dict(nside=2, gamma_w=[1.0], heat_in=[3.0], heat_src=[1.0], T_per_u=10.0, max_iter=100, work=work)
+    # 16 point sources, uniform in the box, photon rates log-uniform over two decades
+    srng = np.random.default_rng(5150)
+    spos = srng.uniform(0.0, 1.0, size=(16, 3)) * np.array([nx, ny, nz], dtype=np.float64)
+    sQ = 1e4 * 10.0 ** srng.uniform(-1.0, 1.0, size=(16, 1))
+    kw = dict(nside=2, gamma_w=[1.0], heat_in=[3.0], heat_src=[1.0], T_per_u=10.0, max_iter=100, work=work,
+              sources=(spos, sQ, [0.5]))
     times, its = [], []
     for _ in range(steps + 1):
         xg.copy_(d(x0))
@@ -552,7 +557,8 @@ def bench_rtchem(steps=3, cpu=True):
            "ms_per_iteration": ms / it, "dt_chem_min": r["dt_chem_min"], "workspace_bytes": int(mesh_ws),
            "higher_is_better": True, "dtype": "f64 (chemistry), f32 (sweep)", "data": "synthetic",
            "config": {"workload": "128^3 lognormal (sigma_ln 1.5) + 16 spheres as n_H, its x_HI; Nside 2, "
-                                  "1 bin, sigma 2, dalpha = 0.38 alpha, dt = 0.3, 81-point synthetic tables"},
+                                  "1 bin, sigma 2, dalpha = 0.38 alpha, 16 point sources (Q 1e3-1e5, e 0.5), "
+                                  "dt = 0.3, 81-point synthetic tables"},
            "roofline": None}
     if cpu:
         from oracle import chem as C
@@ -560,7 +566,8 @@ def bench_rtchem(steps=3, cpu=True):
         cp = C.default_params(nT=81, logT_min=1.0, logT_max=9.0, **tabs)
         cp.update(T_per_u=10.0)
         rp = RC.default_rt_params(nT=81, dalpha=0.38 * alpha, sigma=[2.0], heat_in=[3.0], heat_src=[1.0],
-                                  nside=2)
+                                  nside=2, src_pos=[[2.0, 3.0, 4.0], [6.0, 1.0, 1.5]], src_Q=[[1e3], [1e4]],
+                                  src_e=[0.5])
         shp = (6, 8, 8)
         sn = int(np.prod(shp))
         rng = np.random.default_rng(2)
@@ -570,8 +577,9 @@ def bench_rtchem(steps=3, cpu=True):
         dt = time.perf_counter() - t0
         rec["cpu_baseline"] = {"value": sn * ref["iterations"] / dt, "unit": "cell-iterations/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"a {shp} mesh of the same recipe, {ref['iterations']} iterations "
-                                         f"in {dt:.1f} s (FP64 sweep in C, chemistry in Python loops)"}
+                               "sample": f"a {shp} mesh of the same recipe with 2 sources, {ref['iterations']} "
+                                         f"iterations in {dt:.1f} s (FP64 sweep and point rates in C, "
+                                         "chemistry in Python loops)"}
     mesh.close()
     print(json.dumps(rec), flush=True)
 

@@ -84,7 +84,9 @@ int art_chem_step(long long ncell, const double *n_H, const double *rho, const f
  * The rates are Gamma = sum_b gamma_w_b (J_in_b + S_b) and Heat =
  * sum_b heat_in_b J_in_b + heat_src_b S_b (eqs gamma_diff, heat_diff; with
  * gamma_w_b src_coef_b = 1 the S part of Gamma is the on-the-spot term
- * dalpha n_e n_HII / n_HI).
+ * dalpha n_e n_HII / n_HI).  Point sources (art_point.h: Sect. 2.3,
+ * Appendix A) add their photon-conserving rates per absorber for the same
+ * kappa, with the floored n_HI as the absorber density.
  */
 typedef struct {
     int nbins;               /* 1..ART_MAX_BINS */
@@ -97,6 +99,10 @@ typedef struct {
     int nside;               /* HEALPix resolution of the sweeps, >= 1 */
     double x_floor;          /* in (0, 1] */
     int max_iter;            /* transfer-chemistry iterations, >= 1 */
+    int nsrc;                /* point sources (0: none); their rates are added each iteration */
+    const double *src_pos;   /* host [nsrc][3], as art_point_sources */
+    const double *src_Q;     /* host [nsrc][nbins], as art_point_sources */
+    const double *src_e;     /* host [nbins] or NULL, as art_point_sources */
 } art_rt_chem_params;
 
 typedef struct {
@@ -114,8 +120,9 @@ long long art_rt_chem_workspace(const art_mesh *mesh, int nbins);
  * Advance every cell of the mesh by the radiative step dt.  Iteration i
  * (1 .. max_iter) loads the fields built from the state of iteration i - 1
  * (iteration 0: x_HI, u as given) into the mesh (art_set_fields, with the
- * heating weights), sweeps (art_sweep at nside, I_bc = 0), and advances the
- * given state over dt with those rates (art_chem_step with cp); it stops when
+ * heating weights), sweeps (art_sweep at nside, I_bc = 0), adds the point
+ * sources' rates (art_point_sources), and advances the given state over dt
+ * with those rates (art_chem_step with cp); it stops when
  * every cell with n_H > 0 has |n_e^(i) - n_e^(i-1)| <= eps n_e^(i) and
  * |u^(i) - u^(i-1)| <= eps u^(i) (eps = cp->eps).  Then x_HI and u hold the
  * last iteration's state.  n_H, rho, x_HI, u: device double [cells] (x

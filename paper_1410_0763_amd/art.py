@@ -75,7 +75,8 @@ class RtChemParams(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int), ("sigma", ctypes.c_void_p), ("src_coef", ctypes.c_void_p),
                 ("dalpha", ctypes.c_void_p), ("gamma_w", ctypes.c_void_p), ("heat_in", ctypes.c_void_p),
                 ("heat_src", ctypes.c_void_p), ("nside", ctypes.c_int), ("x_floor", ctypes.c_double),
-                ("max_iter", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("nsrc", ctypes.c_int), ("src_pos", ctypes.c_void_p),
+                ("src_Q", ctypes.c_void_p), ("src_e", ctypes.c_void_p)]
 
 
 class RtChemResult(ctypes.Structure):
@@ -561,13 +562,15 @@ def _farr(vals, nb):
 def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, src_coef, dalpha,
                  nside=1, gamma_w=None, heat_in=None, heat_src=None, x_floor=1e-6, max_iter=100,
                  T_per_u=1.0, eps=1e-3, eps_e=0.2, eps_HI=0.002, chem_max_iter=100, max_sub=100000,
-                 Gamma=None, Heat=None, work=None, stream=None):
+                 sources=None, Gamma=None, Heat=None, work=None, stream=None):
     """art_rt_chem_step: one radiative step of `mesh` coupled to the chemistry.
     n_H, rho, x_HI, u: float64 device tensors of the mesh's cells (x_HI, u
     updated in place); tables: float64 device tensors alpha, k_ci, cool_I,
     cool_II; dalpha: float64 device tensor on the same grid; sigma, src_coef
-    (and the optional weights): per-bin sequences.  Returns dict iterations,
-    converged, dt_chem_min."""
+    (and the optional weights): per-bin sequences; sources: None or (pos
+    (nsrc, 3), Q (nsrc, nbins), e (nbins,) or None) as for point_sources.
+    Returns dict iterations, converged, dt_chem_min."""
+    import numpy as np
     import torch
     L = load()
     nb = len(sigma)
@@ -582,8 +585,18 @@ def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, sr
                     float(eps_HI), int(chem_max_iter), int(max_sub))
     arrs = [_farr(sigma, nb), _farr(src_coef, nb), _farr(gamma_w, nb), _farr(heat_in, nb), _farr(heat_src, nb)]
     cv = [ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs]
+    nsrc, keep = 0, []
+    sp = sq = se = None
+    if sources is not None:
+        pos = np.ascontiguousarray(sources[0], dtype=np.float64).reshape(-1, 3)
+        Qa = np.ascontiguousarray(sources[1], dtype=np.float64).reshape(pos.shape[0], nb)
+        ea = None if len(sources) < 3 or sources[2] is None else np.ascontiguousarray(sources[2], dtype=np.float64)
+        keep = [pos, Qa, ea]
+        nsrc = pos.shape[0]
+        sp, sq = pos.ctypes.data_as(ctypes.c_void_p), Qa.ctypes.data_as(ctypes.c_void_p)
+        se = None if ea is None else ea.ctypes.data_as(ctypes.c_void_p)
     rp = RtChemParams(nb, cv[0], cv[1], _ptr(dalpha), cv[2], cv[3], cv[4], int(nside), float(x_floor),
-                      int(max_iter))
+                      int(max_iter), nsrc, sp, sq, se)
     res = RtChemResult()
     _check(L.art_rt_chem_step(mesh._h, ctypes.byref(rp), ctypes.byref(cp), _ptr(n_H), _ptr(rho), _ptr(x_HI),
                               _ptr(u), float(dt), _ptr(work), int(work.numel()), _ptr(Gamma), _ptr(Heat),

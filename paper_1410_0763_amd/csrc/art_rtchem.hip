@@ -4,8 +4,9 @@
 //
 // The iteration is driven from the host: each pass builds kappa and S from
 // the latest state (one thread per cell, double precision, rounded to the
-// float32 fields the sweep takes), loads them into the mesh, sweeps, advances
-// the start state by dt with art_chem_step, and counts the cells whose n_e or
+// float32 fields the sweep takes), loads them into the mesh, sweeps, adds the
+// point sources' rates, advances the start state by dt with art_chem_step,
+// and counts the cells whose n_e or
 // u moved by more than the tolerance; the count is read back to decide
 // whether to stop.  Every step is an existing library call or a plain
 // per-cell kernel; the convergence count is the only atomic, and it is an
@@ -15,6 +16,7 @@
 
 #include "../../include/art.h"
 #include "../../include/art_chem.h"
+#include "../../include/art_point.h"
 #include "art_internal.h"
 
 #pragma clang fp contract(off)
@@ -42,7 +44,8 @@ __device__ double rtc_tab(const double *__restrict__ t, const RtcArgs &a, double
 __global__ __launch_bounds__(256) void rtc_fields_kernel(long long n, int nb, const double *__restrict__ nH_,
                                                          const double *__restrict__ x_,
                                                          const double *__restrict__ u_, RtcArgs a,
-                                                         float *__restrict__ kappa, float *__restrict__ S)
+                                                         float *__restrict__ kappa, float *__restrict__ S,
+                                                         float *__restrict__ nabs)
 {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -52,10 +55,12 @@ __global__ __launch_bounds__(256) void rtc_fields_kernel(long long n, int nb, co
             kappa[b * n + c] = 0.0f;
             S[b * n + c] = 0.0f;
         }
+        nabs[c] = 0.0f;
         return;
     }
     const double x = x_[c];
     const double nHI = nh * fmax(x, a.x_floor);
+    nabs[c] = (float)nHI;                                    // absorber density of the point-source rates
     const double ne = nh * (1.0 - x);                        // = n_HII
     const double T = a.T_per_u * u_[c] / (1.0 + ne / nh);
     const double da = rtc_tab(a.dalpha, a, T);
@@ -89,6 +94,17 @@ __global__ __launch_bounds__(256) void rtc_check_kernel(long long n, const doubl
 
 __global__ void rtc_zero_kernel(unsigned int *p) { *p = 0u; }
 
+// Gamma += Gp, Heat += Hp (Heat may be absent).
+__global__ __launch_bounds__(256) void rtc_add_kernel(long long n, const float *__restrict__ Gp,
+                                                      const float *__restrict__ Hp, float *__restrict__ G,
+                                                      float *__restrict__ H)
+{
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    G[c] += Gp[c];
+    if (Hp) H[c] += Hp[c];
+}
+
 // Minimum of v over [0, n): per-block minima, then one block over those.
 __global__ __launch_bounds__(256) void rtc_min_kernel(const double *__restrict__ v, long long n,
                                                       double *__restrict__ out)
@@ -109,7 +125,7 @@ __global__ __launch_bounds__(256) void rtc_min_kernel(const double *__restrict__
 constexpr int RTC_MIN_BLOCKS = 1024;
 
 struct Layout {
-    size_t kappa, S, G, H, xa, ua, xb, ub, dtc, cnt, mn, total;
+    size_t kappa, S, G, H, xa, ua, xb, ub, dtc, nabs, Gp, Hp, cnt, mn, total;
 };
 
 Layout layout(long long n, int nb)
@@ -131,6 +147,9 @@ Layout layout(long long n, int nb)
     L.xb = take((size_t)n * 8);
     L.ub = take((size_t)n * 8);
     L.dtc = take((size_t)n * 8);
+    L.nabs = take((size_t)n * 4);
+    L.Gp = take((size_t)n * 4);
+    L.Hp = take((size_t)n * 4);
     L.cnt = take(4);
     L.mn = take((RTC_MIN_BLOCKS + 1) * 8);
     L.total = o;
@@ -195,6 +214,8 @@ extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, co
     if (!(rp->x_floor > 0.0) || !(rp->x_floor <= 1.0))
         return rtc_fail(ART_E_INVAL, "art_rt_chem_step: x_floor must be in (0, 1]");
     if (rp->max_iter < 1) return rtc_fail(ART_E_INVAL, "art_rt_chem_step: max_iter must be >= 1");
+    if (rp->nsrc < 0 || (rp->nsrc > 0 && (!rp->src_pos || !rp->src_Q)))
+        return rtc_fail(ART_E_INVAL, "art_rt_chem_step: nsrc must be >= 0, with positions and photon rates");
     // the chemistry parameters and dt, checked by the chemistry entry point itself
     if (int rc = art_chem_step(0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, dt, cp, nullptr,
                                nullptr, hip_stream))
@@ -213,6 +234,7 @@ extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, co
     double *bx[2] = {(double *)(w + L.xa), (double *)(w + L.xb)};
     double *bu[2] = {(double *)(w + L.ua), (double *)(w + L.ub)};
     double *dtc = (double *)(w + L.dtc), *mn = (double *)(w + L.mn);
+    float *nabs = (float *)(w + L.nabs), *Gp = (float *)(w + L.Gp), *Hp = (float *)(w + L.Hp);
     unsigned int *cnt = (unsigned int *)(w + L.cnt);
 
     RtcArgs a{};
@@ -231,12 +253,21 @@ extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, co
     const double *xp = x_HI, *up = u;                          // iteration 0: the start state
     int it = 0, conv = 0;
     for (it = 1; it <= rp->max_iter; ++it) {
-        hipLaunchKernelGGL(rtc_fields_kernel, dim3(nblk), dim3(256), 0, st, n, nb, n_H, xp, up, a, kap, S);
+        hipLaunchKernelGGL(rtc_fields_kernel, dim3(nblk), dim3(256), 0, st, n, nb, n_H, xp, up, a, kap, S, nabs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail("fields", e);
         if (int rc = art_set_fields(mesh, nb, kap, S, 1, hip_stream)) return rc;
         if (int rc = art_set_heating(mesh, rp->heat_in, rp->heat_src)) return rc;
         if (int rc = art_sweep(mesh, rp->nside, rp->gamma_w, 0.0f, &o, hip_stream)) return rc;
+        if (rp->nsrc > 0) {
+            if (int rc = art_point_sources(mesh, rp->nsrc, rp->src_pos, rp->src_Q, rp->src_e, nabs, Gp,
+                                           rp->src_e ? Hp : nullptr, nullptr, hip_stream))
+                return rc;
+            hipLaunchKernelGGL(rtc_add_kernel, dim3(nblk), dim3(256), 0, st, n, Gp, rp->src_e ? Hp : nullptr,
+                               o.Gamma, o.Heat);
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail("point-source rates", e);
+        }
         double *xn = bx[(it - 1) & 1], *un = bu[(it - 1) & 1];
         e = hipMemcpyAsync(xn, x_HI, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(un, u, (size_t)n * 8, hipMemcpyDeviceToDevice, st);

@@ -96,14 +96,15 @@ def test_rt_chem_argument_checks_without_gpu():
     neg = (ctypes.c_float * 1)(-1.0)
     res = art.RtChemResult()
 
-    def call(nb=1, sig=one, dal=p, nside=1, xf=1e-6, mi=10, dt=1.0, wb=w1, cpp=cp):
+    def call(nb=1, sig=one, dal=p, nside=1, xf=1e-6, mi=10, dt=1.0, wb=w1, cpp=cp, ns=0):
         rp = art.RtChemParams(nb, ctypes.cast(sig, ctypes.c_void_p), ctypes.cast(one, ctypes.c_void_p), dal,
-                              None, None, None, nside, xf, mi)
+                              None, None, None, nside, xf, mi, ns, None, None, None)
         return L.art_rt_chem_step(h, ctypes.byref(rp), ctypes.byref(cpp), p, p, p, p, dt, p, wb, None, None,
                                   ctypes.byref(res), None)
     assert call(nb=0) == -1 and call(nb=5) == -1
     assert call(sig=neg) == -1 and call(dal=None) == -1 and call(nside=0) == -1
     assert call(xf=0.0) == -1 and call(xf=1.5) == -1 and call(mi=0) == -1
+    assert call(ns=-1) == -1 and call(ns=2) == -1                    # sources without positions
     assert call(dt=-1.0) == -1 and call(dt=float("nan")) == -1
     assert call(wb=w1 - 1) == -1 and b"workspace" in L.art_last_error()
     assert call(cpp=art.ChemParams(1, 1.0, 0.1, p, p, p, p, 1.0, 1e-3, 0.2, 0.002, 100, 1000)) == -1

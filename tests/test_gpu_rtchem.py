@@ -34,6 +34,9 @@ def _state(shape, seed):
 
 
 def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter):
+    src = None
+    if rt.get("src_pos") is not None:
+        src = (rt["src_pos"], rt["src_Q"], rt.get("src_e"))
     import torch
     from paper_1410_0763_amd import art
     d = lambda a, t=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(t).cuda()
@@ -46,7 +49,7 @@ def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter):
         r = art.rt_chem_step(mesh, d(nH), d(rho), xg, ug, dt, tables, LT0, (LT1 - LT0) / (NT - 1),
                              rt["sigma"], rt["src_coef"], d(dal), nside=rt["nside"], gamma_w=rt["gamma_w"],
                              heat_in=rt["heat_in"], heat_src=rt["heat_src"], x_floor=rt["x_floor"],
-                             max_iter=max_iter, T_per_u=T_per_u, Gamma=G, Heat=H)
+                             max_iter=max_iter, T_per_u=T_per_u, sources=src, Gamma=G, Heat=H)
         torch.cuda.synchronize()
     return r, xg.cpu().numpy(), ug.cpu().numpy(), G.cpu().numpy().astype(np.float64), \
         H.cpu().numpy().astype(np.float64)
@@ -96,6 +99,53 @@ def test_coupled_step_matches_oracle(nbins, max_iter, dt):
     assert eG <= 1e-5 and eH <= 1e-5
     assert math.isfinite(r["dt_chem_min"]) and abs(r["dt_chem_min"] / ref["dt_chem_min"] - 1) <= 1e-3
     assert np.array_equal(xg[:2], x0[:2]) and np.array_equal(ug[:2], u0[:2])
+
+
+@pytest.mark.parametrize("nbins,max_iter", [(1, 2), (2, 100)])
+def test_coupled_step_with_point_sources_matches_oracle(nbins, max_iter):
+    """Three point sources (one on a cell corner, one on the box face) add
+    their photon-conserving rates each iteration; every cell against the
+    oracle."""
+    shape = (5, 6, 8)
+    print(f"\n== case coupled step with point sources {shape} bins {nbins} max_iter {max_iter}", flush=True)
+    tb, dal, cp, rt = _case(nbins)
+    rt.update(src_pos=[[2.0, 3.0, 1.0], [6.3, 0.0, 4.1], [0.5, 5.5, 2.5]],
+              src_Q=[[30.0, 10.0][:nbins], [5.0, 20.0][:nbins], [12.0, 1.0][:nbins]],
+              src_e=[0.4, 0.9][:nbins])
+    nH, rho, x0, u0 = _state(shape, 70 + nbins)
+    dt = 0.1
+    ref = RC.step(shape, 1.0, nH, rho, x0, u0, dt, rt, cp, max_iter)
+    r, xg, ug, G, H = _run(shape, nH, rho, x0, u0, dt, tb, dal, rt, 10.0, max_iter)
+    ex, eu = _rel(xg, ref["x"]), _rel(ug, ref["u"])
+    sG = np.maximum(np.abs(ref["Gamma"]), 1e-6 * np.abs(ref["Gamma"]).max())
+    sH = np.maximum(np.abs(ref["Heat"]), 1e-6 * np.abs(ref["Heat"]).max())
+    eG, eH = np.max(np.abs(G - ref["Gamma"]) / sG), np.max(np.abs(H - ref["Heat"]) / sH)
+    print(f"iterations {r['iterations']} (oracle {ref['iterations']}), converged {r['converged']}; "
+          f"x_HI {ex.max():.2e}, u {eu.max():.2e}, Gamma {eG:.2e}, Heat {eH:.2e}", flush=True)
+    assert r["iterations"] == ref["iterations"] and r["converged"] == ref["converged"]
+    assert ex.max() <= TOL and eu.max() <= TOL
+    assert eG <= 1e-5 and eH <= 1e-5
+
+
+def test_point_source_thin_column_equilibrium():
+    """The oracle's point-source pin on the GPU: a thin 160-cell column, one
+    source; x_HI at r = 30, 60, 150 solves alpha n (1 - x)^2 = Gamma x with
+    Gamma = sigma Q / (4 pi r^2)."""
+    print("\n== case coupled step, point source in a thin column", flush=True)
+    N, a, sig = 160, 1.0, 1e-9
+    Q = 4.0 * np.pi * 60.0 ** 2 / sig
+    tb = dict(alpha=np.full(NT, a), k_ci=np.zeros(NT), cool_I=np.zeros(NT), cool_II=np.zeros(NT))
+    rt = RC.default_rt_params(sigma=[sig], src_pos=[[0.5, 0.5, 0.5]], src_Q=[[Q]], nside=1)
+    nH = np.ones(N)
+    r, xg, _, G, _ = _run((N, 1, 1), nH, nH, np.full(N, 0.5), np.full(N, 100.0), 200.0, tb,
+                          np.zeros(NT), rt, 1.0, 20)
+    assert r["converged"]
+    for k in (30, 60, 150):
+        Gk = sig * Q / (4.0 * np.pi * k ** 2)
+        x_eq = ((2 * a + Gk) - np.sqrt((2 * a + Gk) ** 2 - 4 * a * a)) / (2 * a)
+        print(f"r {k}: x_HI {xg[k]:.6f}, equilibrium {x_eq:.6f}, Gamma/flux {G[k] / Gk:.5f}", flush=True)
+        assert abs(xg[k] - x_eq) <= 3e-3 * max(x_eq, 1 - x_eq)
+        assert abs(G[k] / Gk - 1) <= 3e-3
 
 
 def test_thick_interior_reaches_the_case_b_balance():
