@@ -27,15 +27,27 @@ struct ChemArgs {
     int max_iter, max_sub;
 };
 
-// Linear interpolation in log10 T, held at the ends.
-__device__ double tab_at(const double *__restrict__ t, const ChemArgs &a, double T)
+// Linear interpolation in log10 T, held at the ends: the position in the
+// grid once per temperature, then the value of each table at it.
+struct TabPos {
+    int i;        // lower node (or the end node where held)
+    double f;     // weight of node i + 1 (0 where held)
+};
+
+__device__ TabPos tab_pos(const ChemArgs &a, double T)
 {
     const double s = (log10(fmax(T, 1e-300)) - a.lt0) / a.dlt;
-    if (s <= 0.0) return t[0];
-    if (s >= (double)(a.nT - 1)) return t[a.nT - 1];
+    if (s <= 0.0) return TabPos{0, 0.0};
+    if (s >= (double)(a.nT - 1)) return TabPos{a.nT - 1, 0.0};
     const int i = (int)floor(s);
-    const double f = s - (double)i;
-    return t[i] * (1.0 - f) + t[i + 1] * f;
+    return TabPos{i, s - (double)i};
+}
+
+__device__ double tab_val(const double *__restrict__ t, const ChemArgs &a, TabPos p)
+{
+    if (p.i >= a.nT - 1) return t[a.nT - 1];
+    if (p.f == 0.0 && p.i == 0) return t[0];
+    return t[p.i] * (1.0 - p.f) + t[p.i + 1] * p.f;
 }
 
 __device__ double temp_of(const ChemArgs &a, double u, double xe) { return a.T_per_u * u / (1.0 + xe); }
@@ -44,8 +56,8 @@ __device__ double temp_of(const ChemArgs &a, double u, double xe) { return a.T_p
 __device__ double dt_chem_of(const ChemArgs &a, double nH, double nHI, double u, double G)
 {
     const double nII = nH - nHI;
-    const double T = temp_of(a, u, nII / nH);
-    const double al = tab_at(a.tab[0], a, T), kc = tab_at(a.tab[1], a, T);
+    const TabPos tp = tab_pos(a, temp_of(a, u, nII / nH));
+    const double al = tab_val(a.tab[0], a, tp), kc = tab_val(a.tab[1], a, tp);
     const double rHI = al * nII * nII - (kc * nII + G) * nHI;   // dn_HI/dt; dn_e/dt = -rHI
     const double te = rHI == 0.0 ? INFINITY : a.eps_e * fabs(nII / rHI);
     const double th = rHI == 0.0 ? INFINITY : a.eps_HI * fabs(nHI / rHI);
@@ -72,8 +84,8 @@ __device__ double u_new(const ChemArgs &a, double u0, double h, double H, double
     const double nII = nH - nHI, xe = nII / nH;
     const double ufl = pow(10.0, a.lt0) / a.T_per_u;
     auto resid = [&](double uu) {
-        const double T = temp_of(a, uu, xe);
-        const double lam = nII * (tab_at(a.tab[2], a, T) * nHI + tab_at(a.tab[3], a, T) * nII);
+        const TabPos tp = tab_pos(a, temp_of(a, uu, xe));
+        const double lam = nII * (tab_val(a.tab[2], a, tp) * nHI + tab_val(a.tab[3], a, tp) * nII);
         return uu - u0 - h * (H * nHI - lam) / rho;
     };
     double lo = ufl, hi = fmax(ufl, u0 + h * H * nHI / rho);
@@ -114,8 +126,8 @@ __global__ __launch_bounds__(256) void art_chem_kernel(long long n, const double
         // one sub-step: species and energy at the advanced time, iterated
         double nHIi = nHI, ui = u, ne_prev = nH - nHI;
         for (int it = 0; it < a.max_iter; ++it) {
-            const double T = temp_of(a, ui, (nH - nHIi) / nH);
-            const double al = tab_at(a.tab[0], a, T), kc = tab_at(a.tab[1], a, T);
+            const TabPos tp = tab_pos(a, temp_of(a, ui, (nH - nHIi) / nH));
+            const double al = tab_val(a.tab[0], a, tp), kc = tab_val(a.tab[1], a, tp);
             const double yn = hi_new(nH, nHI, h, al, kc, G);
             const double un = u_new(a, u, h, H, nH, yn, rho);
             const double ne = nH - yn;
