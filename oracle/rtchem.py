@@ -39,6 +39,11 @@ Readings (the paper gives the model, not the code):
   max_iter iterations (then not converged).  Returned: the state of the last
   iteration, its number, whether it converged, and the minimum chemical
   timestep over the cells at that state (the radiative step is F times it).
+* R4 time stepping (Appendix D).  From t = 0 to t_end: the chemical
+  timestep of the start state, with the rates of its own fields, is that of
+  a step of length 0; then each radiative step is dt = min(F dt_chem_min,
+  t_end - t) with dt_chem_min from the end of the previous step (a step with
+  an infinite dt_chem_min takes the rest at once), until t_end or max_steps.
 """
 from __future__ import annotations
 
@@ -119,6 +124,27 @@ def step(shape, h, nH, rho, x0, u0, dt, rp, cp, max_iter, nthreads=0):
             break
     return dict(x=x_prev, u=u_prev, iterations=it, converged=conv,
                 dt_chem_min=float(np.min(dtc)) if len(dtc) else math.inf, Gamma=G, Heat=H)
+
+
+def advance(shape, h, nH, rho, x0, u0, t_end, F, rp, cp, max_iter, max_steps, nthreads=0):
+    """R4: radiative steps from 0 to t_end.  Returns dict x, u, t, steps,
+    iterations, unconverged, dts (the step lengths), dt_chem_min."""
+    x = np.asarray(x0, np.float64).reshape(-1).copy()
+    u = np.asarray(u0, np.float64).reshape(-1).copy()
+    r = step(shape, h, nH, rho, x, u, 0.0, rp, cp, max_iter, nthreads)
+    dcm = r["dt_chem_min"]
+    t, steps, its, unconv, dts = 0.0, 0, 0, 0, []
+    while t < t_end and steps < max_steps:
+        rest = t_end - t
+        dt = min(F * dcm, rest) if math.isfinite(dcm) else rest
+        r = step(shape, h, nH, rho, x, u, dt, rp, cp, max_iter, nthreads)
+        x, u, dcm = r["x"], r["u"], r["dt_chem_min"]
+        t = t + dt if dt < rest else t_end
+        steps += 1
+        its += r["iterations"]
+        unconv += 0 if r["converged"] else 1
+        dts.append(dt)
+    return dict(x=x, u=u, t=t, steps=steps, iterations=its, unconverged=unconv, dts=dts, dt_chem_min=dcm)
 
 
 def default_rt_params(nbins=1, nT=61, **kw):

@@ -145,6 +145,35 @@ def test_point_source_in_a_thin_column_reaches_photoionisation_equilibrium():
         assert abs(r["Gamma"][k] / G - 1) <= 3e-3
 
 
+def test_advance_follows_photoionisation_in_time():
+    """R4 against the time dependence: a thin column (no recombination, no
+    diffuse emission) under one source, advanced to t_end = 2 in radiative
+    steps of F = 4 chemical timesteps, follows x_HI(t) = x0 e^{-Gamma t}
+    with Gamma = sigma Q / (4 pi r^2) at the chemistry's first-order accuracy:
+    the error falls about tenfold when the timestep factors eps_e, eps_HI
+    (which set both the sub-steps and, through dt_chem, the radiative steps)
+    are ten times smaller; the steps add up to t_end exactly, and the first
+    is F times the chemical timestep of the start state."""
+    N, sig = 80, 1e-9
+    Q = 4.0 * np.pi * 30.0 ** 2 / sig                     # Gamma = 1 at r = 30
+    rp = RC.default_rt_params(sigma=[sig], src_pos=[[0.5, 0.5, 0.5]], src_Q=[[Q]])
+    nH = np.ones(N)
+    exact = 0.9 * math.exp(-1.0 * 2.0)
+    errs = []
+    for scale in (1.0, 0.1):
+        cp = C.default_params()
+        cp.update(eps_e=0.2 * scale, eps_HI=0.002 * scale)
+        r = RC.advance((N, 1, 1), 1.0, nH, nH, np.full(N, 0.9), np.full(N, 100.0), 2.0, 4.0, rp, cp,
+                       max_iter=20, max_steps=100000)
+        assert r["t"] == 2.0 and abs(sum(r["dts"]) - 2.0) <= 1e-12 and r["unconverged"] == 0
+        errs.append(abs(r["x"][30] - exact) / exact)
+    assert errs[0] < 0.3 and 5.0 < errs[0] / errs[1] < 15.0, errs
+    cp = C.default_params()
+    r1 = RC.step((N, 1, 1), 1.0, nH, nH, np.full(N, 0.9), np.full(N, 100.0), 0.0, rp, cp, 20)
+    r = RC.advance((N, 1, 1), 1.0, nH, nH, np.full(N, 0.9), np.full(N, 100.0), 2.0, 4.0, rp, cp, 20, 1)
+    assert r["steps"] == 1 and r["dts"][0] == min(4.0 * r1["dt_chem_min"], 2.0)
+
+
 def test_converged_state_is_a_fixed_point():
     """One more iteration from a converged state moves n_e and u by no more
     than the tolerance (the iteration contracts)."""
