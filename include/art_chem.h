@@ -138,6 +138,30 @@ int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, const art_che
                      void *work, long long work_bytes, float *Gamma, float *Heat,
                      art_rt_chem_result *res, void *hip_stream);
 
+typedef struct {
+    int steps;               /* radiative steps taken */
+    int iterations;          /* transfer-chemistry iterations, all steps */
+    int unconverged;         /* steps that ended at max_iter without converging */
+    double t;                /* time reached: t_end unless max_steps stopped first */
+    double dt_chem_min;      /* minimum chemical timestep at the final state */
+} art_rt_chem_run;
+
+/*
+ * Radiative steps from t = 0 to t_end (Appendix D): the chemical timestep of
+ * the start state, with the rates of its own fields, is that of a step of
+ * length 0 (which leaves x_HI and u as they are); then each step is art_rt_chem_step over dt = min(F dt_chem_min,
+ * t_end - t), dt_chem_min from the end of the previous step (the rest at
+ * once where it is infinite), until t_end or max_steps steps.  The paper
+ * sets F = 1-10.  Arguments as art_rt_chem_step; t_end finite and >= 0,
+ * F > 0 and finite, max_steps >= 1.  x_HI and u hold the final state;
+ * Gamma and Heat (or NULL) the last iteration's rates.  run: host, filled on
+ * success.  Blocks the host like art_rt_chem_step.
+ */
+int art_rt_chem_advance(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
+                        const double *n_H, const double *rho, double *x_HI, double *u, double t_end,
+                        double F, int max_steps, void *work, long long work_bytes, float *Gamma,
+                        float *Heat, art_rt_chem_run *run, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

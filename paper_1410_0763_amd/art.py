@@ -39,7 +39,7 @@ SG_EXPORTS = ("art_surrogate_create", "art_surrogate_destroy", "art_surrogate_n_
 # include/art_point.h: rates from point sources
 PT_EXPORTS = ("art_point_sources", "art_point_sources_noalloc")
 # include/art_chem.h: chemistry and energy update of a radiative step
-CHEM_EXPORTS = ("art_chem_step", "art_rt_chem_workspace", "art_rt_chem_step")
+CHEM_EXPORTS = ("art_chem_step", "art_rt_chem_workspace", "art_rt_chem_step", "art_rt_chem_advance")
 # include/art_diag.h: measurements behind design decisions
 DIAG_EXPORTS = ("art_diag_release_cost",)
 
@@ -81,6 +81,11 @@ class RtChemParams(ctypes.Structure):
 
 class RtChemResult(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("dt_chem_min", ctypes.c_double)]
+
+
+class RtChemRun(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("iterations", ctypes.c_int), ("unconverged", ctypes.c_int),
+                ("t", ctypes.c_double), ("dt_chem_min", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -172,6 +177,9 @@ def load(path: str = LIB_PATH):
     L.art_rt_chem_step.argtypes = [vp, ctypes.POINTER(RtChemParams), ctypes.POINTER(ChemParams), vp, vp,
                                    vp, vp, d, vp, ctypes.c_longlong, vp, vp, ctypes.POINTER(RtChemResult),
                                    vp]
+    L.art_rt_chem_advance.argtypes = [vp, ctypes.POINTER(RtChemParams), ctypes.POINTER(ChemParams), vp, vp,
+                                      vp, vp, d, d, i, vp, ctypes.c_longlong, vp, vp,
+                                      ctypes.POINTER(RtChemRun), vp]
     L.art_diag_release_cost.argtypes = [i, i, ctypes.POINTER(ctypes.c_float)]
     for name in EXPORTS + NN_EXPORTS + SG_EXPORTS + PT_EXPORTS + CHEM_EXPORTS + DIAG_EXPORTS:
         if name not in ("art_last_error", "art_rt_chem_workspace"):
@@ -559,17 +567,11 @@ def _farr(vals, nb):
     return None if vals is None else (ctypes.c_float * nb)(*[float(v) for v in vals])
 
 
-def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, src_coef, dalpha,
-                 nside=1, gamma_w=None, heat_in=None, heat_src=None, x_floor=1e-6, max_iter=100,
-                 T_per_u=1.0, eps=1e-3, eps_e=0.2, eps_HI=0.002, chem_max_iter=100, max_sub=100000,
-                 sources=None, Gamma=None, Heat=None, work=None, stream=None):
-    """art_rt_chem_step: one radiative step of `mesh` coupled to the chemistry.
-    n_H, rho, x_HI, u: float64 device tensors of the mesh's cells (x_HI, u
-    updated in place); tables: float64 device tensors alpha, k_ci, cool_I,
-    cool_II; dalpha: float64 device tensor on the same grid; sigma, src_coef
-    (and the optional weights): per-bin sequences; sources: None or (pos
-    (nsrc, 3), Q (nsrc, nbins), e (nbins,) or None) as for point_sources.
-    Returns dict iterations, converged, dt_chem_min."""
+def _rt_chem_args(mesh, n_H, tables, logT_min, dlogT, sigma, src_coef, dalpha, nside, gamma_w, heat_in,
+                  heat_src, x_floor, max_iter, T_per_u, eps, eps_e, eps_HI, chem_max_iter, max_sub, sources,
+                  work):
+    """Parameter blocks of the coupled step (and the host arrays they point
+    into, which must stay alive for the call)."""
     import numpy as np
     import torch
     L = load()
@@ -585,20 +587,56 @@ def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, sr
                     float(eps_HI), int(chem_max_iter), int(max_sub))
     arrs = [_farr(sigma, nb), _farr(src_coef, nb), _farr(gamma_w, nb), _farr(heat_in, nb), _farr(heat_src, nb)]
     cv = [ctypes.cast(a, ctypes.c_void_p) if a is not None else None for a in arrs]
-    nsrc, keep = 0, []
+    nsrc, keep = 0, list(arrs)
     sp = sq = se = None
     if sources is not None:
         pos = np.ascontiguousarray(sources[0], dtype=np.float64).reshape(-1, 3)
         Qa = np.ascontiguousarray(sources[1], dtype=np.float64).reshape(pos.shape[0], nb)
         ea = None if len(sources) < 3 or sources[2] is None else np.ascontiguousarray(sources[2], dtype=np.float64)
-        keep = [pos, Qa, ea]
+        keep += [pos, Qa, ea]
         nsrc = pos.shape[0]
         sp, sq = pos.ctypes.data_as(ctypes.c_void_p), Qa.ctypes.data_as(ctypes.c_void_p)
         se = None if ea is None else ea.ctypes.data_as(ctypes.c_void_p)
     rp = RtChemParams(nb, cv[0], cv[1], _ptr(dalpha), cv[2], cv[3], cv[4], int(nside), float(x_floor),
                       int(max_iter), nsrc, sp, sq, se)
+    return rp, cp, work, keep
+
+
+def rt_chem_step(mesh, n_H, rho, x_HI, u, dt, tables, logT_min, dlogT, sigma, src_coef, dalpha,
+                 nside=1, gamma_w=None, heat_in=None, heat_src=None, x_floor=1e-6, max_iter=100,
+                 T_per_u=1.0, eps=1e-3, eps_e=0.2, eps_HI=0.002, chem_max_iter=100, max_sub=100000,
+                 sources=None, Gamma=None, Heat=None, work=None, stream=None):
+    """art_rt_chem_step: one radiative step of `mesh` coupled to the chemistry.
+    n_H, rho, x_HI, u: float64 device tensors of the mesh's cells (x_HI, u
+    updated in place); tables: float64 device tensors alpha, k_ci, cool_I,
+    cool_II; dalpha: float64 device tensor on the same grid; sigma, src_coef
+    (and the optional weights): per-bin sequences; sources: None or (pos
+    (nsrc, 3), Q (nsrc, nbins), e (nbins,) or None) as for point_sources.
+    Returns dict iterations, converged, dt_chem_min."""
+    rp, cp, work, keep = _rt_chem_args(mesh, n_H, tables, logT_min, dlogT, sigma, src_coef, dalpha, nside,
+                                       gamma_w, heat_in, heat_src, x_floor, max_iter, T_per_u, eps, eps_e,
+                                       eps_HI, chem_max_iter, max_sub, sources, work)
     res = RtChemResult()
-    _check(L.art_rt_chem_step(mesh._h, ctypes.byref(rp), ctypes.byref(cp), _ptr(n_H), _ptr(rho), _ptr(x_HI),
-                              _ptr(u), float(dt), _ptr(work), int(work.numel()), _ptr(Gamma), _ptr(Heat),
-                              ctypes.byref(res), _stream_ptr(stream)))
+    _check(load().art_rt_chem_step(mesh._h, ctypes.byref(rp), ctypes.byref(cp), _ptr(n_H), _ptr(rho),
+                                   _ptr(x_HI), _ptr(u), float(dt), _ptr(work), int(work.numel()), _ptr(Gamma),
+                                   _ptr(Heat), ctypes.byref(res), _stream_ptr(stream)))
     return dict(iterations=res.iterations, converged=bool(res.converged), dt_chem_min=res.dt_chem_min)
+
+
+def rt_chem_advance(mesh, n_H, rho, x_HI, u, t_end, F, tables, logT_min, dlogT, sigma, src_coef, dalpha,
+                    max_steps=100000, nside=1, gamma_w=None, heat_in=None, heat_src=None, x_floor=1e-6,
+                    max_iter=100, T_per_u=1.0, eps=1e-3, eps_e=0.2, eps_HI=0.002, chem_max_iter=100,
+                    max_sub=100000, sources=None, Gamma=None, Heat=None, work=None, stream=None):
+    """art_rt_chem_advance: radiative steps of F chemical timesteps from 0 to
+    t_end (arguments as rt_chem_step).  Returns dict steps, iterations,
+    unconverged, t, dt_chem_min."""
+    rp, cp, work, keep = _rt_chem_args(mesh, n_H, tables, logT_min, dlogT, sigma, src_coef, dalpha, nside,
+                                       gamma_w, heat_in, heat_src, x_floor, max_iter, T_per_u, eps, eps_e,
+                                       eps_HI, chem_max_iter, max_sub, sources, work)
+    run = RtChemRun()
+    _check(load().art_rt_chem_advance(mesh._h, ctypes.byref(rp), ctypes.byref(cp), _ptr(n_H), _ptr(rho),
+                                      _ptr(x_HI), _ptr(u), float(t_end), float(F), int(max_steps), _ptr(work),
+                                      int(work.numel()), _ptr(Gamma), _ptr(Heat), ctypes.byref(run),
+                                      _stream_ptr(stream)))
+    return dict(steps=run.steps, iterations=run.iterations, unconverged=run.unconverged, t=run.t,
+                dt_chem_min=run.dt_chem_min)

@@ -11,6 +11,7 @@
 // whether to stop.  Every step is an existing library call or a plain
 // per-cell kernel; the convergence count is the only atomic, and it is an
 // integer sum (the same on every run).
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -195,10 +196,13 @@ extern "C" long long art_rt_chem_workspace(const art_mesh *mesh, int nbins)
     return (long long)layout(mesh_cells(mesh), nbins).total;
 }
 
-extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
-                                const double *n_H, const double *rho, double *x_HI, double *u, double dt,
-                                void *work, long long work_bytes, float *Gamma, float *Heat,
-                                art_rt_chem_result *res, void *hip_stream)
+namespace {
+
+// One coupled step; keep_start leaves x_HI and u as they came in (the step of
+// length 0 that gives the chemical timestep of the start state).
+int rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp, const double *n_H,
+                 const double *rho, double *x_HI, double *u, double dt, void *work, long long work_bytes,
+                 float *Gamma, float *Heat, art_rt_chem_result *res, void *hip_stream, bool keep_start)
 {
     if (!mesh || !rp || !cp || !res) return rtc_fail(ART_E_INVAL, "art_rt_chem_step: null mesh, parameters or result");
     if (!n_H || !rho || !x_HI || !u || !work)
@@ -290,9 +294,12 @@ extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, co
         }
     }
     if (it > rp->max_iter) it = rp->max_iter;
-    hipError_t e = hipMemcpyAsync(x_HI, xp, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(u, up, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail("state copy", e);
+    hipError_t e = hipSuccess;
+    if (!keep_start) {
+        e = hipMemcpyAsync(x_HI, xp, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(u, up, (size_t)n * 8, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail("state copy", e);
+    }
     const unsigned nmb = nblk < (unsigned)RTC_MIN_BLOCKS ? nblk : (unsigned)RTC_MIN_BLOCKS;
     hipLaunchKernelGGL(rtc_min_kernel, dim3(nmb), dim3(256), 0, st, dtc, n, mn);
     hipLaunchKernelGGL(rtc_min_kernel, dim3(1), dim3(256), 0, st, mn, (long long)nmb, mn + RTC_MIN_BLOCKS);
@@ -304,5 +311,53 @@ extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, co
     res->iterations = it;
     res->converged = conv;
     res->dt_chem_min = dmin;
+    return ART_OK;
+}
+
+}  // namespace
+
+extern "C" int art_rt_chem_step(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
+                                const double *n_H, const double *rho, double *x_HI, double *u, double dt,
+                                void *work, long long work_bytes, float *Gamma, float *Heat,
+                                art_rt_chem_result *res, void *hip_stream)
+{
+    return rt_chem_step(mesh, rp, cp, n_H, rho, x_HI, u, dt, work, work_bytes, Gamma, Heat, res, hip_stream,
+                        false);
+}
+
+extern "C" int art_rt_chem_advance(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
+                                   const double *n_H, const double *rho, double *x_HI, double *u,
+                                   double t_end, double F, int max_steps, void *work, long long work_bytes,
+                                   float *Gamma, float *Heat, art_rt_chem_run *run, void *hip_stream)
+{
+    if (!run) return rtc_fail(ART_E_INVAL, "art_rt_chem_advance: null result");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end))
+        return rtc_fail(ART_E_INVAL, "art_rt_chem_advance: t_end must be finite and >= 0");
+    if (!(F > 0.0) || !std::isfinite(F)) return rtc_fail(ART_E_INVAL, "art_rt_chem_advance: F must be finite and > 0");
+    if (max_steps < 1) return rtc_fail(ART_E_INVAL, "art_rt_chem_advance: max_steps must be >= 1");
+    art_rt_chem_result r{};
+    // the chemical timestep of the start state: a step of length 0
+    if (int rc = rt_chem_step(mesh, rp, cp, n_H, rho, x_HI, u, 0.0, work, work_bytes, Gamma, Heat, &r,
+                              hip_stream, true))
+        return rc;
+    double dcm = r.dt_chem_min, t = 0.0;
+    int steps = 0, its = 0, unconv = 0;
+    while (t < t_end && steps < max_steps) {
+        const double rest = t_end - t;
+        const double dt = std::isfinite(dcm) ? std::min(F * dcm, rest) : rest;
+        if (int rc = art_rt_chem_step(mesh, rp, cp, n_H, rho, x_HI, u, dt, work, work_bytes, Gamma, Heat, &r,
+                                      hip_stream))
+            return rc;
+        dcm = r.dt_chem_min;
+        t = dt < rest ? t + dt : t_end;
+        ++steps;
+        its += r.iterations;
+        unconv += r.converged ? 0 : 1;
+    }
+    run->steps = steps;
+    run->iterations = its;
+    run->unconverged = unconv;
+    run->t = t;
+    run->dt_chem_min = dcm;
     return ART_OK;
 }

@@ -108,6 +108,16 @@ def test_rt_chem_argument_checks_without_gpu():
     assert call(dt=-1.0) == -1 and call(dt=float("nan")) == -1
     assert call(wb=w1 - 1) == -1 and b"workspace" in L.art_last_error()
     assert call(cpp=art.ChemParams(1, 1.0, 0.1, p, p, p, p, 1.0, 1e-3, 0.2, 0.002, 100, 1000)) == -1
+    run = art.RtChemRun()
+
+    def adv(nb=1, t_end=1.0, F=1.0, ms=10, out=run):
+        rp = art.RtChemParams(nb, ctypes.cast(one, ctypes.c_void_p), ctypes.cast(one, ctypes.c_void_p), p,
+                              None, None, None, 1, 1e-6, 10, 0, None, None, None)
+        return L.art_rt_chem_advance(h, ctypes.byref(rp), ctypes.byref(cp), p, p, p, p, t_end, F, ms, p, w1,
+                                     None, None, None if out is None else ctypes.byref(out), None)
+    assert adv(t_end=-1.0) == -1 and adv(t_end=float("inf")) == -1 and adv(t_end=float("nan")) == -1
+    assert adv(F=0.0) == -1 and adv(F=float("inf")) == -1 and adv(ms=0) == -1 and adv(out=None) == -1
+    assert adv(nb=0) == -1 and b"nbins" in L.art_last_error()          # the step's own checks come first
     assert L.art_destroy_mesh(h) == 0
 
 

@@ -2,7 +2,9 @@
 iteration, Sect. 2.2 fields) against the FP64 oracle (oracle/rtchem.py):
 every cell after 1, 2 and 3 forced iterations and after convergence, the
 iteration counts, the last iteration's rates; the thick-interior case-B
-balance; a 64^3 step for timing, bounds and bitwise repeatability."""
+balance; a 64^3 step for timing, bounds and bitwise repeatability.  The time
+stepping (art_rt_chem_advance, Appendix D) against the oracle's, and against
+exponential photo-ionisation."""
 import math
 
 import numpy as np
@@ -33,7 +35,9 @@ def _state(shape, seed):
     return nH, nH * 1.2, x, u
 
 
-def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter):
+def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter, advance=None, **chem):
+    """art_rt_chem_step over dt, or with advance=(t_end, F, max_steps)
+    art_rt_chem_advance; chem: the chemistry's timestep factors."""
     src = None
     if rt.get("src_pos") is not None:
         src = (rt["src_pos"], rt["src_Q"], rt.get("src_e"))
@@ -45,11 +49,16 @@ def _run(shape, nH, rho, x, u, dt, tb, dal, rt, T_per_u, max_iter):
     xg, ug = d(x), d(u)
     G = torch.zeros(len(nH), dtype=torch.float32, device="cuda")
     H = torch.zeros_like(G)
+    kw = dict(nside=rt["nside"], gamma_w=rt["gamma_w"], heat_in=rt["heat_in"], heat_src=rt["heat_src"],
+              x_floor=rt["x_floor"], max_iter=max_iter, T_per_u=T_per_u, sources=src, Gamma=G, Heat=H, **chem)
     with art.Mesh(nx, ny, nz) as mesh:
-        r = art.rt_chem_step(mesh, d(nH), d(rho), xg, ug, dt, tables, LT0, (LT1 - LT0) / (NT - 1),
-                             rt["sigma"], rt["src_coef"], d(dal), nside=rt["nside"], gamma_w=rt["gamma_w"],
-                             heat_in=rt["heat_in"], heat_src=rt["heat_src"], x_floor=rt["x_floor"],
-                             max_iter=max_iter, T_per_u=T_per_u, sources=src, Gamma=G, Heat=H)
+        if advance is None:
+            r = art.rt_chem_step(mesh, d(nH), d(rho), xg, ug, dt, tables, LT0, (LT1 - LT0) / (NT - 1),
+                                 rt["sigma"], rt["src_coef"], d(dal), **kw)
+        else:
+            t_end, F, max_steps = advance
+            r = art.rt_chem_advance(mesh, d(nH), d(rho), xg, ug, t_end, F, tables, LT0, (LT1 - LT0) / (NT - 1),
+                                    rt["sigma"], rt["src_coef"], d(dal), max_steps=max_steps, **kw)
         torch.cuda.synchronize()
     return r, xg.cpu().numpy(), ug.cpu().numpy(), G.cpu().numpy().astype(np.float64), \
         H.cpu().numpy().astype(np.float64)
@@ -166,6 +175,64 @@ def test_thick_interior_reaches_the_case_b_balance():
           f"{a / (a + k):.6f}", flush=True)
     assert r["converged"]
     assert abs(xg[62] - xb) <= 3e-3 * max(xb, 1 - xb)
+
+
+# Over n radiative steps the error of each step (TOL) is carried into the
+# next one at most unamplified (the start state enters the backward-difference
+# and energy updates with a factor within [0, 1]): n TOL bounds the sum.
+@pytest.mark.parametrize("max_steps", [1, 3, 100])
+def test_advance_matches_oracle(max_steps):
+    """art_rt_chem_advance from 0 to 1 in steps of F = 2 chemical timesteps
+    (eleven, the first 2 dt_chem of the start state, the last clipped to the
+    end) under two point sources, against the oracle's time stepping: the
+    step and iteration counts, the time reached, every cell; with max_steps 1
+    and 3 the run stops early at the oracle's time."""
+    shape = (5, 6, 8)
+    print(f"\n== case coupled advance {shape} t_end 1 F 2 max_steps {max_steps}", flush=True)
+    tb, dal, cp, rt = _case(1)
+    rt.update(src_pos=[[2.0, 3.0, 1.0], [6.3, 0.0, 4.1]], src_Q=[[30.0], [5.0]], src_e=[0.4])
+    nH, rho, x0, u0 = _state(shape, 91)
+    ref = RC.advance(shape, 1.0, nH, rho, x0, u0, 1.0, 2.0, rt, cp, 100, max_steps)
+    r, xg, ug, _, _ = _run(shape, nH, rho, x0, u0, None, tb, dal, rt, 10.0, 100, advance=(1.0, 2.0, max_steps))
+    ex, eu = _rel(xg, ref["x"]), _rel(ug, ref["u"])
+    print(f"steps {r['steps']} (oracle {ref['steps']}), iterations {r['iterations']} (oracle "
+          f"{ref['iterations']}), t {r['t']:.9g} (oracle {ref['t']:.9g}), unconverged {r['unconverged']}; "
+          f"x_HI {ex.max():.2e}, u {eu.max():.2e}; dt_chem_min {r['dt_chem_min']:.6e} (oracle "
+          f"{ref['dt_chem_min']:.6e})", flush=True)
+    assert r["steps"] == ref["steps"] == min(max_steps, 11)
+    assert r["iterations"] == ref["iterations"] and r["unconverged"] == ref["unconverged"] == 0
+    if max_steps >= 11:
+        assert r["t"] == ref["t"] == 1.0
+    else:
+        assert abs(r["t"] / ref["t"] - 1) <= 1e-3
+    assert ex.max() <= ref["steps"] * TOL and eu.max() <= ref["steps"] * TOL
+    assert abs(r["dt_chem_min"] / ref["dt_chem_min"] - 1) <= 1e-3
+    assert np.array_equal(xg[:2], x0[:2]) and np.array_equal(ug[:2], u0[:2])
+
+
+def test_advance_follows_photoionisation_in_time():
+    """The oracle's time-stepping pin on the GPU: a thin column under one
+    source (no recombination, no diffuse emission) advanced to t_end = 2 in
+    steps of F = 4 chemical timesteps follows x_HI = x0 e^{-Gamma t},
+    Gamma = 1 at r = 30, to first order: the error falls about tenfold with
+    timestep factors ten times smaller."""
+    print("\n== case coupled advance, photo-ionisation in a thin column", flush=True)
+    N, sig = 80, 1e-9
+    Q = 4.0 * np.pi * 30.0 ** 2 / sig
+    z = np.zeros(NT)
+    tb = dict(alpha=z, k_ci=z, cool_I=z, cool_II=z)
+    rt = RC.default_rt_params(sigma=[sig], src_pos=[[0.5, 0.5, 0.5]], src_Q=[[Q]])
+    nH = np.ones(N)
+    exact = 0.9 * math.exp(-2.0)
+    errs = []
+    for scale in (1.0, 0.1):
+        r, xg, _, G, _ = _run((N, 1, 1), nH, nH, np.full(N, 0.9), np.full(N, 100.0), None, tb, z, rt, 1.0, 20,
+                              advance=(2.0, 4.0, 100000), eps_e=0.2 * scale, eps_HI=0.002 * scale)
+        errs.append(abs(xg[30] - exact) / exact)
+        print(f"timestep factors x{scale}: {r['steps']} steps, {r['iterations']} iterations, x_HI(r=30) "
+              f"{xg[30]:.6f}, exact {exact:.6f}, Gamma {G[30]:.6f}", flush=True)
+        assert r["t"] == 2.0 and r["unconverged"] == 0 and abs(G[30] - 1.0) <= 1e-3
+    assert errs[0] < 0.3 and 5.0 < errs[0] / errs[1] < 15.0, errs
 
 
 def test_coupled_step_64_cubed():
