@@ -37,10 +37,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
 WORKLOAD = ("plain_256: 256^3 lognormal (sigma_ln 1.5) + 64 spheres (kappa x100), "
             "HEALPix nside 8 (768 directions), 4 frequency bins, FP32")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_plain_256_traffic.json")
 MARCH_SRC = os.path.join(ROOT, "paper_1410_0763_amd", "csrc", "art_march.hip")
+
+
+def copy_rate_gbs(nbytes=2 << 30, reps=5):
+    """HBM rate a plain device-to-device copy of nbytes reaches on this GPU
+    (bytes read + written per second, in GB/s), measured after the timed
+    region: what streaming code attains here, beside the published peak."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
 def march_source_hash():
@@ -830,7 +853,22 @@ def main():
                                "(achieved = algorithmic bytes per launch / average launch time)"},
         "cpu_baseline": None,
     }
+    # the plain-VALU ceiling beside the HBM one: per segment-bin the method's
+    # arithmetic is about 10 FP32 operations and one exponential (a quarter
+    # of the rate: 4 issue slots), against 1024 SIMDs x 16 lanes x 2.4 GHz of
+    # FP32 issue without packed math
+    slots = 14
+    valu_floor_ms = 1e3 * seg_bins * slots / VALU_LANE_RATE
+    rec["valu_ceiling"] = {"slots_per_segment_bin": slots, "lane_slots_per_s": VALU_LANE_RATE,
+                           "floor_ms": valu_floor_ms, "march_ms": 1e3 * march_s,
+                           "frac": valu_floor_ms / (1e3 * march_s)}
+    rec["config"]["sweep_ms_median"] = float(sorted(sweep_ms)[len(sweep_ms) // 2])
     mesh.close()
+    ph.push("device copy reference")
+    copy = copy_rate_gbs()
+    rec["roofline"]["copy_GBps"] = copy
+    rec["roofline"]["frac_of_copy"] = achieved / copy
+    ph.pop()
     if not args.no_cpu_baseline:
         ph.push("cpu baseline (oracle)")
         rec["cpu_baseline"] = cpu_baseline(m)

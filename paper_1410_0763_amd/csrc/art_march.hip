@@ -517,13 +517,12 @@ template <int NB, int K>
 hipError_t launch_nbk(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, size_t bytes,
                       int threads, unsigned int *seg_count, hipStream_t stream)
 {
-    static size_t configured = 64 * 1024;   // up to 64 KiB needs no opt-in
-    if (bytes > configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)art_march_kernel<NB, K>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        configured = bytes;
-    }
+    // Up to 64 KiB of local memory needs no opt-in; beyond, one opt-in to the
+    // whole of it, made once (a function-local static: thread-safe).
+    static const hipError_t cfg = hipFuncSetAttribute((const void *)art_march_kernel<NB, K>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      art_march_max_lds_bytes());
+    if (bytes > 64 * 1024 && cfg != hipSuccess) return cfg;
     if (nitems <= 0) return hipSuccess;   // a call without items only configures the kernel
     hipLaunchKernelGGL((art_march_kernel<NB, K>), dim3(nitems), dim3(threads), bytes, stream, items,
                        meshes, seg_count);
