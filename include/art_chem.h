@@ -155,7 +155,9 @@ typedef struct {
  * sets F = 1-10.  Arguments as art_rt_chem_step; t_end finite and >= 0,
  * F > 0 and finite, max_steps >= 1.  x_HI and u hold the final state;
  * Gamma and Heat (or NULL) the last iteration's rates.  run: host, filled on
- * success.  Blocks the host like art_rt_chem_step.
+ * success.  Blocks the host like art_rt_chem_step.  ART_E_INVAL for a bad
+ * argument, ART_E_STATE if the chemical timestep falls to 0 before t_end
+ * (the state then holds the steps taken), or the code of a failing step.
  */
 int art_rt_chem_advance(art_mesh *mesh, const art_rt_chem_params *rp, const art_chem_params *cp,
                         const double *n_H, const double *rho, double *x_HI, double *u, double t_end,

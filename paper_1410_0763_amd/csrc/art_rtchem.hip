@@ -345,6 +345,8 @@ extern "C" int art_rt_chem_advance(art_mesh *mesh, const art_rt_chem_params *rp,
     while (t < t_end && steps < max_steps) {
         const double rest = t_end - t;
         const double dt = std::isfinite(dcm) ? std::min(F * dcm, rest) : rest;
+        if (!(dt > 0.0))   // a chemical timestep of 0 would never reach t_end
+            return rtc_fail(ART_E_STATE, "art_rt_chem_advance: the chemical timestep fell to 0");
         if (int rc = art_rt_chem_step(mesh, rp, cp, n_H, rho, x_HI, u, dt, work, work_bytes, Gamma, Heat, &r,
                                       hip_stream))
             return rc;
