@@ -583,6 +583,20 @@ def bench_rtchem(steps=3, cpu=True):
                                   "1 bin, sigma 2, dalpha = 0.38 alpha, 16 point sources (Q 1e3-1e5, e 0.5), "
                                   "dt = 0.3, 81-point synthetic tables"},
            "roofline": None}
+    # the same interval in radiative steps of F = 4 minimum chemical timesteps
+    # (art_rt_chem_advance, time stepping of Appendix D)
+    xg.copy_(d(x0))
+    ug.copy_(d(u0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a = art.rt_chem_advance(mesh, nH, rho, xg, ug, 0.3, 4.0, tables, 1.0, 0.1, [2.0], [1.0], dal, **kw)
+    torch.cuda.synchronize()
+    ams = (time.perf_counter() - t0) * 1e3
+    rec["advance"] = {"t_end": 0.3, "F": 4.0, "steps": a["steps"], "iterations": a["iterations"],
+                      "unconverged": a["unconverged"], "t": a["t"], "ms": ams,
+                      "cell_iterations_per_s": n * (a["iterations"] + 1) / (ams / 1e3),
+                      "note": "iterations over the radiative steps plus the length-0 step that gives the "
+                              "first chemical timestep"}
     if cpu:
         from oracle import chem as C
         from oracle import rtchem as RC

@@ -252,3 +252,24 @@ def test_coupled_step_64_cubed():
     assert np.array_equal(x1, x2) and np.array_equal(u1, u2)
     floor = 10.0 ** LT0 / 10.0
     assert np.all((x1 >= 0) & (x1 <= 1)) and np.all(u1 >= floor)
+
+
+def test_advance_64_cubed():
+    """64^3, Nside 2, four point sources, four radiative steps of F = 2:
+    every step converges, the state stays in bounds, the steps add up to the
+    time reached, and a second run repeats the first bit for bit."""
+    print("\n== case coupled advance 64^3, 4 sources, 4 steps", flush=True)
+    tb, dal, cp, rt = _case(1)
+    rng = np.random.default_rng(64)
+    rt.update(src_pos=rng.uniform(0.0, 64.0, size=(4, 3)), src_Q=10.0 ** rng.uniform(1, 3, size=(4, 1)),
+              src_e=[0.5])
+    shape = (64, 64, 64)
+    nH, rho, x0, u0 = _state(shape, 78)
+    runs = [_run(shape, nH, rho, x0, u0, None, tb, dal, rt, 10.0, 100, advance=(100.0, 2.0, 4)) for _ in range(2)]
+    (r1, x1, u1, _, _), (r2, x2, u2, _, _) = runs
+    print(f"steps {r1['steps']}, iterations {r1['iterations']}, unconverged {r1['unconverged']}, "
+          f"t {r1['t']:.6e}, dt_chem_min {r1['dt_chem_min']:.4e}", flush=True)
+    assert r1 == r2 and np.array_equal(x1, x2) and np.array_equal(u1, u2)
+    assert r1["steps"] == 4 and r1["unconverged"] == 0 and 0.0 < r1["t"] < 100.0
+    floor = 10.0 ** LT0 / 10.0
+    assert np.all((x1 >= 0) & (x1 <= 1)) and np.all(u1 >= floor)
