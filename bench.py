@@ -37,8 +37,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_LANE_RATE = 256 * 4 * 16 * 2.4e9
 WORKLOAD = ("plain_256: 256^3 lognormal (sigma_ln 1.5) + 64 spheres (kappa x100), "
             "HEALPix nside 8 (768 directions), 4 frequency bins, FP32")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "march_plain_256_traffic.json")
@@ -872,8 +870,8 @@ def main():
     # of the rate: 4 issue slots), against 1024 SIMDs x 16 lanes x 2.4 GHz of
     # FP32 issue without packed math
     slots = 14
-    valu_floor_ms = 1e3 * seg_bins * slots / VALU_LANE_RATE
-    rec["valu_ceiling"] = {"slots_per_segment_bin": slots, "lane_slots_per_s": VALU_LANE_RATE,
+    valu_floor_ms = 1e3 * seg_bins * slots / VALU_LANE_PEAK
+    rec["valu_ceiling"] = {"slots_per_segment_bin": slots, "lane_slots_per_s": VALU_LANE_PEAK,
                            "floor_ms": valu_floor_ms, "march_ms": 1e3 * march_s,
                            "frac": valu_floor_ms / (1e3 * march_s)}
     rec["config"]["sweep_ms_median"] = float(sorted(sweep_ms)[len(sweep_ms) // 2])

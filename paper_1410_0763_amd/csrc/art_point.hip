@@ -14,9 +14,10 @@
 // art_set_fields: half the cache lines and a quarter of the load instructions
 // of reading the records bin by bin.  Sources arrive 64 per
 // launch as kernel arguments; the first launch writes the outputs, later ones
-// add to them.  Every cell index is clamped to the mesh before its load, and
-// the walk takes exactly the |dx| + |dy| + |dz| cell moves between the
-// source's cell and the target.
+// add to them.  The pack is read through a buffer descriptor with 32-bit
+// byte offsets (a cell index outside the mesh reads 0 and never touches
+// memory), and the walk takes exactly the |dx| + |dy| + |dz| cell moves
+// between the source's cell and the target.
 #include <cmath>
 #include <string>
 
@@ -42,16 +43,20 @@ struct PtChunk {
     int has_e;
 };
 
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // One step of the cell walk: the segment from t to the nearest plane
-// crossing (its cell, clamped to the mesh, and its length), then the move to
-// the next cell across that plane (ties: x, y, z).
+// crossing (its cell and its length), then the move to the next cell across
+// that plane (ties: x, y, z).
 __device__ __forceinline__ void walk_step(double &tnx, double &tny, double &tnz, double &t, int &cell,
                                           int dcx, int dcy, int dcz, double dtx, double dty,
-                                          double dtz, int ncell, int &cl, double &dl)
+                                          double dtz, int &cl, double &dl)
 {
     const double tmin = fmin(tnx, fmin(tny, tnz));
     dl = tmin - t;
-    cl = min(max(cell, 0), ncell - 1);
+    cl = cell;
     t = tmin;
     const bool mx = tnx == tmin;
     const bool my = !mx && tny == tmin;
@@ -61,26 +66,29 @@ __device__ __forceinline__ void walk_step(double &tnx, double &tny, double &tnz,
     tnz += (!mx && !my) ? dtz : 0.0;
 }
 
-// kappa h of the NB bins of one cell from the pack (KS floats per cell).
+// kappa h of the NB bins of one cell from the pack (KS floats per cell);
+// an index outside the pack reads 0.
 template <int NB, int KS>
-__device__ __forceinline__ void load_kh(const float *__restrict__ kp, int cell, float *kh)
+__device__ __forceinline__ void load_kh(rsrc_t kp, int cell, float *kh)
 {
+    const unsigned off = (unsigned)cell * (unsigned)(KS * 4);
     if constexpr (KS == 4) {
-        const float4 v = reinterpret_cast<const float4 *>(kp)[cell];
-        const float a[4] = {v.x, v.y, v.z, v.w};
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(kp, off, 0, 0);
+        const float a[4] = {__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                            __uint_as_float(v.w)};
 #pragma unroll
         for (int b = 0; b < NB; ++b) kh[b] = a[b];
     } else if constexpr (KS == 2) {
-        const float2 v = reinterpret_cast<const float2 *>(kp)[cell];
-        kh[0] = v.x;
-        if constexpr (NB > 1) kh[1] = v.y;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(kp, off, 0, 0);
+        kh[0] = __uint_as_float(v.x);
+        if constexpr (NB > 1) kh[1] = __uint_as_float(v.y);
     } else {
-        kh[0] = kp[cell];
+        kh[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(kp, off, 0, 0));
     }
 }
 
 template <int NB, int KS>
-__global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict__ kp,
+__global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict__ kpack,
                                                         const float *__restrict__ n_abs, int nx,
                                                         int ny, int nz, double h, PtChunk src,
                                                         int first, float *__restrict__ Gamma,
@@ -98,7 +106,10 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
     if (cx >= nx || cy >= ny || cz >= nz) return;
     const int cid = (cz * ny + cy) * nx + cx;
     const double na = (double)n_abs[cid];
-    const int ncell = nx * ny * nz;
+    // the pack, KS floats per cell (below 2^31 bytes: checked by the host)
+    const rsrc_t kp = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(kpack), (short)0,
+                                                        (int)((unsigned)(nx * ny * nz) * (unsigned)(KS * 4)),
+                                                        0x00020000);
     const double vol_c = (4.0 * M_PI / 3.0) * h * h * h;
     double g = 0.0, ht = 0.0;
     unsigned nseg = 0;
@@ -154,8 +165,7 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
         // runs from the (k-1)-th to the k-th crossing, the last crossing being
         // r_in.  Groups of four steps of geometry, then their four loads, then
         // their sums, so that four loads are in flight per lane; the last
-        // nmove mod 4 steps one by one.  The cell index is clamped to the
-        // mesh before every load.
+        // nmove mod 4 steps one by one.
         const int nmove = abs(cx - ix) + abs(cy - iy) + abs(cz - iz);
         double t = 0.0;
         int k = 0;
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
             double dl[PT_UNROLL];
 #pragma unroll
             for (int u = 0; u < PT_UNROLL; ++u)
-                walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, ncell, cl[u], dl[u]);
+                walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, cl[u], dl[u]);
             float kh[PT_UNROLL][NB];
 #pragma unroll
             for (int u = 0; u < PT_UNROLL; ++u) load_kh<NB, KS>(kp, cl[u], kh[u]);
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
         for (; k < nmove; ++k) {                  // the last nmove mod 4 steps
             int cl;
             double dl;
-            walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, ncell, cl, dl);
+            walk_step(tnx, tny, tnz, t, cell, dcx, dcy, dcz, dtx, dty, dtz, cl, dl);
             float kh[NB];
             load_kh<NB, KS>(kp, cl, kh);
 #pragma unroll
@@ -260,6 +270,11 @@ int art_point_impl(art_mesh *mesh, int nsrc, const double *pos, const double *Q,
     if (!n_abs || !Gamma) return pt_fail(ART_E_INVAL, "art_point_sources: null n_abs or Gamma");
     if ((long long)dims[0] * dims[1] * dims[2] * nb >= 0x7fffffffll)
         return pt_fail(ART_E_UNSUPPORTED, "art_point_sources: more than 2^31 - 1 records");
+    {
+        const long long ks_ = nb == 1 ? 1 : (nb == 2 ? 2 : 4);
+        if ((long long)dims[0] * dims[1] * dims[2] * ks_ * 4 >= 0x80000000ll)
+            return pt_fail(ART_E_UNSUPPORTED, "art_point_sources: kappa pack of 2 GiB or more");
+    }
     for (int s = 0; s < nsrc; ++s) {
         for (int ax = 0; ax < 3; ++ax) {
             const double v = pos[3 * s + ax];
