@@ -109,21 +109,25 @@ __device__ __forceinline__ void load_slot(rsrc_t r, unsigned off, float *v)
     }
 }
 
+// Ray states are read again only by a later launch, so they are stored with
+// the non-temporal cache policy (bit 1 of the policy operand, `nt`).
+#define ART_STATE_STORE_POLICY 2
+
 template <int NB>
 __device__ __forceinline__ void store_slot(rsrc_t r, unsigned off, const float *v)
 {
     if constexpr (NB == 4) {
         const u32x4 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                          __float_as_uint(v[3])};
-        __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, ART_STATE_STORE_POLICY);
     } else if constexpr (NB == 3) {
         const u32x3 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
-        __builtin_amdgcn_raw_buffer_store_b96(x, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b96(x, r, off, 0, ART_STATE_STORE_POLICY);
     } else if constexpr (NB == 2) {
         const u32x2 x = {__float_as_uint(v[0]), __float_as_uint(v[1])};
-        __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, ART_STATE_STORE_POLICY);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, off, 0, ART_STATE_STORE_POLICY);
     }
 }
 
