@@ -75,6 +75,8 @@ typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef __attribute__((address_space(1))) float g_f;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f32x4 g_f32x4;
 typedef __attribute__((address_space(4))) const ArtDir c_dir;
 typedef __attribute__((address_space(4))) const int c_int;
 
@@ -496,16 +498,58 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     __syncthreads();
     if (threadIdx.x == 0) seg_count[blockIdx.x] = *wg_count;
 
-    // Flush: this workgroup is the only writer of its block in this bucket's copy.
+    // Flush: this workgroup is the only writer of its block in this bucket's
+    // copy.  The stores follow the copy's x-fastest order: for dominant axis y
+    // or z a tile row runs along x, and four of its cells go out as one
+    // 16-byte store where the copy is 16-byte aligned; for dominant axis x the
+    // slabs of a column run along x, so consecutive threads take consecutive
+    // slabs.  (Component-fastest or tile-row-fastest orders scatter each store
+    // instruction over 8 or 64 cache lines and made the march 7-9% slower.)
     g_f *dst = (g_f *)M.acc + (long long)it_bucket * NB * 2 * M.ncell;
-    for (int idx = threadIdx.x; idx < NB * 2 * V; idx += blockDim.x) {
-        const int comp = idx % (2 * NB), cell = idx / (2 * NB);
-        const int la = cell >> 6, l = cell & 63;
-        const int cb = lo_b + (bneg ? 7 - (l & 7) : (l & 7));
-        const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
-        if (la >= nslab || cb >= Nb || cc >= Nc) continue;
-        const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
-        dst[comp * M.ncell + wc] = accl[idx];
+    if (cls != 0 && (M.ncell & 3) == 0 && (M.nx & 3) == 0) {
+        const int ng = nslab * 16;                // groups of four cells per component
+        for (int idx = threadIdx.x; idx < NB * 2 * ng; idx += blockDim.x) {
+            const int comp = idx / ng, q = idx % ng;
+            const int la = q >> 4, rw = (q >> 1) & 7, half = q & 1;
+            const int cc = lo_c + rw;             // the tile row's c index
+            if (cc >= Nc) continue;
+            const int cb0 = lo_b + 4 * half;      // its first cell along b = x
+            const int rwl = cneg ? 7 - rw : rw;   // the lane row holding it
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int cbk = 4 * half + k;
+                v[k] = accl[(la * 64 + rwl * 8 + (bneg ? 7 - cbk : cbk)) * (2 * NB) + comp];
+            }
+            const long long wc = (lo_a + la) * sa + (long long)cb0 * sb + (long long)cc * sc;
+            if (cb0 + 3 < Nb) {
+                *(g_f32x4 *)&dst[comp * M.ncell + wc] = f32x4{v[0], v[1], v[2], v[3]};
+            } else {
+                for (int k = 0; k < 4; ++k)
+                    if (cb0 + k < Nb) dst[comp * M.ncell + wc + k] = v[k];
+            }
+        }
+    } else if (cls == 0) {
+        const int nq = nslab * 64;
+        for (int idx = threadIdx.x; idx < NB * 2 * nq; idx += blockDim.x) {
+            const int comp = idx / nq, q = idx % nq;
+            const int l = q / nslab, la = q % nslab;
+            const int cb = lo_b + (bneg ? 7 - (l & 7) : (l & 7));
+            const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
+            if (cb >= Nb || cc >= Nc) continue;
+            const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
+            dst[comp * M.ncell + wc] = accl[(la * 64 + l) * (2 * NB) + comp];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < NB * 2 * V; idx += blockDim.x) {
+            const int comp = idx / V, cell = idx % V;
+            const int la = cell >> 6, l = cell & 63;
+            const int cb = lo_b + (bneg ? 7 - (l & 7) : (l & 7));
+            const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
+            if (la >= nslab || cb >= Nb || cc >= Nc) continue;
+            const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
+            dst[comp * M.ncell + wc] = accl[cell * (2 * NB) + comp];
+        }
     }
 }
 
