@@ -83,6 +83,7 @@ struct art_mesh {
     int *order = nullptr; size_t order_cap = 0;
     int *bucket_start = nullptr; size_t bs_cap = 0;
     float *state = nullptr; size_t state_cap = 0;
+    float *faces = nullptr; size_t faces_cap = 0;
     uint4 *geo = nullptr; size_t geo_cap = 0;
     float *acc = nullptr; size_t acc_cap = 0;
 
@@ -235,6 +236,25 @@ long long dir_slot_bound(const art_mesh *m)
     return worst;
 }
 
+// Blocks of the largest block cross-section over the three dominant axes.
+long long face_blocks(const art_mesh *m)
+{
+    const long long N[3] = {m->nx, m->ny, m->nz};
+    long long worst = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        worst = std::max(worst, ((N[b] + 7) / 8) * ((N[c] + 7) / 8));
+    }
+    return worst;
+}
+
+// Face-buffer floats of one direction: b- and c-faces of two block layers
+// along a (depth slabs x 8 rays per block), a-faces (64 rays per block).
+long long face_dir_floats(const art_mesh *m)
+{
+    return (4ll * m->tune.depth * 8 + 64) * face_blocks(m) * m->nb;
+}
+
 long long state_bound(const art_mesh *m, int nd)
 {
     const long long N[3] = {m->nx, m->ny, m->nz};
@@ -264,15 +284,18 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
             (1ll << 31) ||
         (m->tune.depth + 14ll) * std::max((long long)m->nx * m->ny, (long long)m->ny * m->nz) * m->nb * 8 >=
             (1ll << 31) ||
-        (long long)nd * std::max(m->nx, std::max(m->ny, m->nz)) * 16 >= (1ll << 31))
+        (long long)nd * std::max(m->nx, std::max(m->ny, m->nz)) * 16 >= (1ll << 31) ||
+        (long long)m->mbd * face_dir_floats(m) * 4 >= (1ll << 31))
         return fail(ART_E_UNSUPPORTED, "mesh too large for 32-bit offsets within a bucket of directions or a block");
     const int nbk = 24 * m->tune.subsets;
     const int gstride = std::max(m->nx, std::max(m->ny, m->nz));
     const size_t need_state = (size_t)state_bound(m, nd), need_geo = (size_t)nd * gstride;
     const size_t need_acc = (size_t)nbk * m->nb * 2 * m->ncell;
+    const size_t need_faces = (size_t)nbk * m->mbd * face_dir_floats(m);
     if (m->batches > 0 &&
         ((size_t)nd > m->dirs_cap || (size_t)nd > m->order_cap || (size_t)nbk + 1 > m->bs_cap ||
-         need_state > m->state_cap || need_geo > m->geo_cap || need_acc > m->acc_cap))
+         need_state > m->state_cap || need_geo > m->geo_cap || need_acc > m->acc_cap ||
+         need_faces > m->faces_cap))
         return fail(ART_E_STATE, "this sweep would reallocate buffers of a mesh held by a live batch "
                                  "(larger Nside than the batch's); destroy the batch first");
     const void *tab_bufs[5] = {m->dirs, m->order, m->bucket_start, m->state, m->geo};
@@ -283,6 +306,7 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     if ((rc = dev_alloc(&m->state, need_state, &m->state_cap))) return rc;
     if ((rc = dev_alloc(&m->geo, need_geo, &m->geo_cap))) return rc;
     if ((rc = dev_alloc(&m->acc, need_acc, &m->acc_cap))) return rc;
+    if ((rc = dev_alloc(&m->faces, need_faces, &m->faces_cap))) return rc;
     if (tab_bufs[0] != m->dirs || tab_bufs[1] != m->order || tab_bufs[2] != m->bucket_start ||
         tab_bufs[3] != m->state || tab_bufs[4] != m->geo)
         m->tab_valid = false;   // new buffers hold no tables
@@ -291,6 +315,10 @@ int prepare(art_mesh *m, int nside, float I_bc, hipStream_t st)
     d.fields = m->fields;
     d.fields_t = m->fields_t;
     d.state = m->state;
+    d.faces = m->faces;
+    d.face_dir_floats = face_dir_floats(m);
+    d.face_bucket_dirs = m->mbd;
+    d.face_P = (int)face_blocks(m);
     d.acc = m->acc;
     d.dirs = m->dirs;
     d.order = m->order;
@@ -557,7 +585,7 @@ int art_destroy_mesh(art_mesh *m)
     if (!m) return ART_OK;
     if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch; destroy the batch first");
     void *bufs[] = {m->fields, m->fields_t, m->bad, m->stage, m->dirs, m->order, m->bucket_start,
-                    m->state, m->geo, m->acc, m->items, m->desc, m->seg_count, m->kpack};
+                    m->state, m->faces, m->geo, m->acc, m->items, m->desc, m->seg_count, m->kpack};
     for (hipEvent_t e : m->ev)
         if (e) (void)hipEventDestroy(e);
     for (void *p : bufs)

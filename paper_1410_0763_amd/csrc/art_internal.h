@@ -32,7 +32,11 @@ struct ArtDir {
 struct ArtMeshDesc {
     const float2 *fields;      // [cell][nb] = {kappa h, S}, cells x fastest
     const float2 *fields_t;    // the same with y fastest, then z, then x
-    float *state;              // ray intensities handed from block to block
+    float *state;              // ray intensities where rays leave the mesh
+    float *faces;              // rays handed from block to block (block-face buffers)
+    long long face_dir_floats; // face-buffer floats per direction
+    int face_bucket_dirs;      // directions per bucket the face buffers hold
+    int face_P;                // blocks of the largest cross-section (b x c)
     float *acc;                // [bucket][nb][2][cell] per-bucket direction sums
     const ArtDir *dirs;        // [N_d]
     const int *order;          // direction indices grouped by bucket

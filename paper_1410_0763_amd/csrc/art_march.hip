@@ -10,7 +10,9 @@
 // wavefront w (the sum of block indices counted along the group's travel
 // directions) only receive rays from wavefronts < w, which earlier launches on
 // the same stream have finished; a ray's intensity crosses block faces through
-// its state slot.  Each workgroup stores its block into its bucket's own
+// face buffers laid out by block face (a move's rays, or a tile's, are one
+// contiguous run), and the intensity with which it leaves the mesh goes to
+// its ray-state slot.  Each workgroup stores its block into its bucket's own
 // accumulator copy with plain stores: no other workgroup writes those cells of
 // that copy, so no global atomics are needed (the single-writer property that
 // Sect. 3.1 obtains with ray groups).
@@ -25,8 +27,8 @@
 // bucket travel the same way along b and c, so the lane-to-column map is
 // mirrored per bucket such that a move always hands lane l - 1's ray to lane
 // l along b (a DPP row shift) and lane l - 8's ray along c (ds_bpermute); edge
-// lanes hand rays to and from the neighbouring blocks through the state
-// buffer.  A lane reads its own cell's fields once per slab and adds its
+// lanes hand rays to and from the neighbouring blocks through the face
+// buffers.  A lane reads its own cell's fields once per slab and adds its
 // contributions to its own cell once per slab.  The per-(direction, slab)
 // pattern comes from a table built once per sweep (segment lengths and a code
 // word naming the moves in order); the code word goes to a scalar register, so
@@ -40,14 +42,13 @@
 // entries are loaded one slab ahead.
 //
 // Memory is addressed through buffer descriptors with 32-bit byte offsets
-// (wave-uniform bases in scalar registers): the bucket's state region, the
-// block's field records and the table.  A lane that must not store (it is not
-// at the tile edge the rays leave through, or outside the mesh) stores to an
-// offset beyond the descriptor's range, which the hardware drops; a load there
-// returns 0 without touching memory.  Each direction's state region starts
-// with a boundary slot holding I_bc, read by every lane whose ray enters
-// through a mesh face; with I_bc = 0 those lanes, and lanes that need no ray
-// in a slab, read out of range instead.
+// (wave-uniform bases in scalar registers): the bucket's face buffers and
+// ray-state region, the block's field records and the table.  A lane that must
+// not store (it is not at the tile edge the rays leave through, or outside the
+// mesh) stores to an offset beyond the descriptor's range, which the hardware
+// drops; a load there returns 0 without touching memory.  Lanes whose ray
+// enters through a mesh face, and lanes that need no ray in a slab, read out
+// of range and take I_bc from a register.
 //
 // Field records are {kappa h, S} per (cell, bin), 8 bytes, all bins of a cell
 // together; directions whose dominant axis is x read a second copy with y
@@ -92,44 +93,46 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *p, unsigned bytes)
 // A byte offset no descriptor here reaches (every range is below 2^31 bytes).
 #define ART_OOB 0x80000000u
 
-// The NB floats of a ray-state slot.
+// The NB floats of a ray (a ray-state slot or a face-buffer entry) at byte
+// offset off + soff (soff wave-uniform).
 template <int NB>
-__device__ __forceinline__ void load_slot(rsrc_t r, unsigned off, float *v)
+__device__ __forceinline__ void load_slot(rsrc_t r, unsigned off, float *v, unsigned soff = 0)
 {
     if constexpr (NB == 4) {
-        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0);
         v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y);
         v[2] = __uint_as_float(x.z); v[3] = __uint_as_float(x.w);
     } else if constexpr (NB == 3) {
-        const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+        const u32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, off, soff, 0);
         v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y); v[2] = __uint_as_float(x.z);
     } else if constexpr (NB == 2) {
-        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0);
         v[0] = __uint_as_float(x.x); v[1] = __uint_as_float(x.y);
     } else {
-        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+        v[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
     }
 }
 
-// Ray states are read again only by a later launch, so they are stored with
-// the non-temporal cache policy (bit 1 of the policy operand, `nt`).
+// Rays handed to another block are read again only by a later launch, so
+// they are stored with the non-temporal cache policy (bit 1 of the policy
+// operand, `nt`).
 #define ART_STATE_STORE_POLICY 2
 
 template <int NB>
-__device__ __forceinline__ void store_slot(rsrc_t r, unsigned off, const float *v)
+__device__ __forceinline__ void store_slot(rsrc_t r, unsigned off, const float *v, unsigned soff = 0)
 {
     if constexpr (NB == 4) {
         const u32x4 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                          __float_as_uint(v[3])};
-        __builtin_amdgcn_raw_buffer_store_b128(x, r, off, 0, ART_STATE_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, off, soff, ART_STATE_STORE_POLICY);
     } else if constexpr (NB == 3) {
         const u32x3 x = {__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2])};
-        __builtin_amdgcn_raw_buffer_store_b96(x, r, off, 0, ART_STATE_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b96(x, r, off, soff, ART_STATE_STORE_POLICY);
     } else if constexpr (NB == 2) {
         const u32x2 x = {__float_as_uint(v[0]), __float_as_uint(v[1])};
-        __builtin_amdgcn_raw_buffer_store_b64(x, r, off, 0, ART_STATE_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, off, soff, ART_STATE_STORE_POLICY);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, off, 0, ART_STATE_STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), r, off, soff, ART_STATE_STORE_POLICY);
     }
 }
 
@@ -267,21 +270,29 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     // (cl, rw) owns tile column cl, or 7 - cl if bneg (row rw, or 7 - rw if
     // cneg): a b-move then always hands the ray of lane cl - 1 to lane cl (DPP
     // row shift), a c-move that of lane - 8 to the lane.  At a move the lane
-    // stores its ray if it leaves the tile or the mesh (Lb / Lc), takes the
-    // neighbour lane's ray (Tb / Tc), or loads a ray arriving from the
-    // neighbouring tile (Nb / Nc; otherwise a ray entering the mesh, I_bc).
+    // stores its ray if it leaves the tile (Fb / Fc, to the face buffer) or
+    // the mesh (Xb / Xc, to its ray-state slot), takes the neighbour lane's
+    // ray (Tb / Tc), or loads a ray arriving from the neighbouring tile
+    // (Nb / Nc; otherwise a ray entering the mesh, I_bc).
     const int cl = lane & 7, rw = lane >> 3;
     const bool bneg = (oct >> ab) & 1, cneg = (oct >> ac) & 1;
     const int gb = lo_b + (bneg ? 7 - cl : cl), gc = lo_c + (cneg ? 7 - rw : rw);
     const bool in_dom = gb < Nb && gc < Nc;
     const int gbs = bneg ? gb + 1 : gb - 1;               // column a b-move brings a ray from
     const int gcs = cneg ? gc + 1 : gc - 1;
-    const bool Lb = in_dom && (cl == 7 || (bneg ? gb == 0 : gb + 1 >= Nb));
+    const bool Xb = in_dom && (bneg ? gb == 0 : gb + 1 >= Nb);   // leaves the mesh
+    const bool Fb = in_dom && cl == 7 && !Xb;                      // leaves the tile
     const bool Tb = cl >= 1 && gbs < Nb;
     const bool Nb_ = in_dom && cl == 0 && gbs >= 0 && gbs < Nb;
-    const bool Lc = in_dom && (rw == 7 || (cneg ? gc == 0 : gc + 1 >= Nc));
+    const bool Xc = in_dom && (cneg ? gc == 0 : gc + 1 >= Nc);
+    const bool Fc = in_dom && rw == 7 && !Xc;
     const bool Tc = rw >= 1 && gcs < Nc;
     const bool Nc_ = in_dom && rw == 0 && gcs >= 0 && gcs < Nc;
+    // blocks with lanes on the mesh's exit faces along b and c, and the last
+    // block along a (wave-uniform)
+    const bool edge_b = bneg ? lo_b == 0 : lo_b + 8 >= Nb;
+    const bool edge_c = cneg ? lo_c == 0 : lo_c + 8 >= Nc;
+    const bool last_a = d0 + nslab >= Na;
     const int csrc4 = (rw >= 1 ? lane - 8 : lane) << 2;   // ds_bpermute byte address
 
     // LDS accumulators: per cell of the block, {A1, A2} of every bin.
@@ -312,20 +323,49 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     c_dir *dirs = (c_dir *)M.dirs;
     c_int *order = (c_int *)M.order;
     const int gstride = M.geo_stride;
-    // The bucket's ray states are one contiguous range (boundary slot of its
-    // first direction up to the last ray of its last direction).
+    // The bucket's ray states (exit intensities) are one contiguous range
+    // (boundary slot of its first direction up to the last ray of its last
+    // direction).
     const long long sbase = dirs[order[dbeg]].state_off - NB;
     const c_dir &Dl = dirs[order[dend - 1]];
     const rsrc_t rS = make_rsrc(M.state + sbase,
                                 (unsigned)((Dl.state_off + (long long)Dl.nj * Dl.nk * NB - sbase) * 4));
     unsigned int sseg = 0;   // segments of positive length per in-mesh lane (wave-uniform)
     const bool zero_bc = M.I_bc == 0.0f;
+    const float Ibc = M.I_bc;
+
+    // Face buffers.  A ray that crosses from this block into a neighbouring
+    // one is handed over by block face: per direction of the bucket, b-faces
+    // [a-parity][block][slab of the block][lane row], c-faces [a-parity]
+    // [block][slab][lane column] and a-faces [block][lane], with blocks
+    // numbered b + nbb c; the 8 rays of a move, and the 64 of a tile, are one
+    // contiguous run.  The neighbour along b or c reads the entry in the next
+    // launch, on the same slab, before the block two steps on along a
+    // reuses it; the next block along a reads the a-face.  A ray that leaves
+    // the mesh goes to its ray-state slot instead (its exit intensity).
+    const unsigned es = NB * 4;                           // bytes of one ray
+    const unsigned slab_b = 8 * es;                       // one slab of a block face
+    const unsigned fb_sz = 2u * (unsigned)M.face_P * (unsigned)depth * slab_b;
+    const unsigned fdir = (unsigned)(M.face_dir_floats * 4);
+    const rsrc_t rX = make_rsrc(M.faces + (long long)it_bucket * M.face_bucket_dirs * M.face_dir_floats,
+                                fdir * (unsigned)M.face_bucket_dirs);
+    const int par = pa & 1;
+    const int pb_n = bneg ? pb + 1 : pb - 1, pc_n = cneg ? pc + 1 : pc - 1;   // upstream neighbours
+    const unsigned pbc = (unsigned)(pb + nbb * pc);
+    const unsigned pbc_b = (unsigned)((pb_n >= 0 && pb_n < nbb ? pb_n : pb) + nbb * pc);
+    const unsigned pbc_c = (unsigned)(pb + nbb * (pc_n >= 0 && pc_n < nbc ? pc_n : pc));
+    const unsigned fbw = (par * (unsigned)M.face_P + pbc) * (unsigned)depth * slab_b;
+    const unsigned fbr = (par * (unsigned)M.face_P + pbc_b) * (unsigned)depth * slab_b;
+    const unsigned fcw = fb_sz + (par * (unsigned)M.face_P + pbc) * (unsigned)depth * slab_b;
+    const unsigned fcr = fb_sz + (par * (unsigned)M.face_P + pbc_c) * (unsigned)depth * slab_b;
+    const unsigned fa = 2u * fb_sz + pbc * 64u * es;
+    const unsigned rwo = (unsigned)rw * es, clo = (unsigned)cl * es, lno = (unsigned)lane * es;
 
     for (int q0 = dbeg + wave; q0 < dend; q0 += nwave * K) {
         bool act[K];
         unsigned gvoff[K];      // byte offset of the direction's first table row
         unsigned dB[K], dC[K];  // state offset change of a b-move, a c-move
-        unsigned dbase[K];      // byte offset of the direction's boundary slot in rS
+        unsigned dirb[K];       // byte offset of the direction's face buffers in rX
         unsigned cur[K];        // byte offset of the lane's current ray in rS
         float invw[K], invwl[K], wdir[K];
         float I[K][NB];
@@ -347,14 +387,16 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             cur[m] = db + (unsigned)((1 + (gc - Bc - D.k0) * sk + (gb - Bb - D.j0) * sj) * NB * 4);
             dB[m] = in_vgpr((unsigned)((bneg ? -1 : 1) * sj * NB * 4));
             dC[m] = in_vgpr((unsigned)((cneg ? -1 : 1) * sk * NB * 4));
-            // boundary slot (I_bc); with I_bc = 0 an out-of-range offset, which
-            // reads 0 without touching memory
-            dbase[m] = in_vgpr(zero_bc ? ART_OOB : db);
+            dirb[m] = (unsigned)((act[m] ? q : q0) - dbeg) * fdir;
             invw[m] = in_vgpr((float)D.invw);
             invwl[m] = in_vgpr((float)(-D.invw * 1.4426950408889634));
             wdir[m] = in_vgpr((float)D.w);
             // rays entering through the top face come from the block above
-            load_slot<NB>(rS, (in_dom && d0 > 0) ? cur[m] : dbase[m], I[m]);
+            // (its a-face entry), or from outside the mesh (I_bc)
+            load_slot<NB>(rX, (in_dom && d0 > 0) ? lno : ART_OOB, I[m], dirb[m] + fa);
+            if (!zero_bc)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) I[m][b] = (in_dom && d0 > 0) ? I[m][b] : Ibc;
             gcur[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)(d0 * 16), 0);
         }
         float kh[NB], Sv[NB];
@@ -378,10 +420,15 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             for (int m = 0; m < K; ++m) {
                 const unsigned c1 = codes[m] & 3u, c2 = (codes[m] >> 2) & 3u;
                 const bool hb = c1 == 1u || c2 == 1u, hc = c1 == 2u || c2 == 2u;
-                const unsigned ob = cur[m] - dB[m] - (c1 == 2u ? dC[m] : 0u);
-                const unsigned oc = cur[m] - dC[m] - (c1 == 1u ? dB[m] : 0u);
-                load_slot<NB>(rS, (hb && Nb_) ? ob : dbase[m], ib[m]);
-                load_slot<NB>(rS, (hc && Nc_) ? oc : dbase[m], ic[m]);
+                load_slot<NB>(rX, (hb && Nb_) ? rwo : ART_OOB, ib[m], dirb[m] + fbr + (unsigned)t * slab_b);
+                load_slot<NB>(rX, (hc && Nc_) ? clo : ART_OOB, ic[m], dirb[m] + fcr + (unsigned)t * slab_b);
+                if (!zero_bc) {     // rays entering the mesh
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        ib[m][b] = Nb_ ? ib[m][b] : Ibc;
+                        ic[m][b] = Nc_ ? ic[m][b] : Ibc;
+                    }
+                }
                 gnext[m] = __builtin_amdgcn_raw_buffer_load_b128(rG, gvoff[m], (unsigned)((i + 1) * 16), 0);
             }
             // |n_a| / (kappa h) per direction and bin (1/0 = inf: vacuum takes the
@@ -404,7 +451,8 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 
             // a b-move: every ray moves one column; lane cl takes lane cl - 1's ray
             auto cross_b = [&](int m) {
-                store_slot<NB>(rS, Lb ? cur[m] : ART_OOB, I[m]);
+                store_slot<NB>(rX, Fb ? rwo : ART_OOB, I[m], dirb[m] + fbw + (unsigned)t * slab_b);
+                if (edge_b) store_slot<NB>(rS, Xb ? cur[m] : ART_OOB, I[m]);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     const float moved =
@@ -415,7 +463,8 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             };
             // a c-move: every ray moves one row; the lane takes lane - 8's ray
             auto cross_c = [&](int m) {
-                store_slot<NB>(rS, Lc ? cur[m] : ART_OOB, I[m]);
+                store_slot<NB>(rX, Fc ? clo : ART_OOB, I[m], dirb[m] + fcw + (unsigned)t * slab_b);
+                if (edge_c) store_slot<NB>(rS, Xc ? cur[m] : ART_OOB, I[m]);
                 float moved[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
@@ -483,10 +532,15 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int m = 0; m < K; ++m) gcur[m] = gnext[m];
         }
-        // rays leave through the block's far face (into the next block or out of the mesh)
+        // rays leave through the block's far face: into the next block's
+        // a-face entry, or out of the mesh into their ray-state slots
 #pragma unroll
-        for (int m = 0; m < K; ++m)
-            store_slot<NB>(rS, (act[m] && in_dom) ? cur[m] : ART_OOB, I[m]);
+        for (int m = 0; m < K; ++m) {
+            if (last_a)
+                store_slot<NB>(rS, (act[m] && in_dom) ? cur[m] : ART_OOB, I[m]);
+            else
+                store_slot<NB>(rX, (act[m] && in_dom) ? lno : ART_OOB, I[m], dirb[m] + fa);
+        }
     }
 
     // workgroup total of marched segments of positive length (work accounting)
