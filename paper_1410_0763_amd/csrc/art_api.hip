@@ -387,8 +387,24 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
     const int lds_floats = art_march_lds_floats(m->tune.depth, m->nb);
     for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
         const int n = m->wave_off[w + 1] - m->wave_off[w];
-        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, m->tune.interleave,
-                                lds_floats, 64 * m->tune.waves, m->seg_count + m->wave_off[w], st));
+        // The launches of the wavefront ramps hold few workgroups, and each
+        // takes as long as one workgroup alone: there, with one wave per
+        // workgroup tuned, 4 (or 2) waves share a workgroup's directions, each
+        // with its own accumulators.  Fixed thresholds (a quarter and a half
+        // of 3072 workgroups, the resident one-wave workgroups of 256 CUs), so
+        // that which blocks take the multi-wave sums does not depend on the GPU.
+        int waves = m->tune.waves, priv = 0, lf = lds_floats;
+        if (waves == 1)
+            for (int W : {4, 2})
+                if (n * W <= 3072 &&
+                    (long long)art_march_lds_floats(m->tune.depth, m->nb, W) * 4 <= art_march_max_lds_bytes()) {
+                    waves = W;
+                    priv = 1;
+                    lf = art_march_lds_floats(m->tune.depth, m->nb, W);
+                    break;
+                }
+        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, m->tune.interleave, lf,
+                                64 * waves, m->seg_count + m->wave_off[w], st, priv));
     }
     HIPCHK(hipEventRecord(m->ev[2], st));
     return ART_OK;

@@ -67,9 +67,11 @@ struct ArtItem {
 hipError_t art_launch_dirs(int nside, int nx, int ny, int nz, int nb, int d_begin, int d_end,
                            int subsets, ArtDir *dirs, int *order, int *bucket_start, uint4 *geo,
                            int geo_stride, float *state, float I_bc, hipStream_t stream);
+// priv != 0 with more than one wave per workgroup: each wave accumulates in
+// its own local-memory region (lds_floats must cover threads / 64 regions).
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,
-                            hipStream_t stream);
+                            hipStream_t stream, int priv = 0);
 hipError_t art_launch_check(const float *kappa, const float *S, long long n, int *bad_flag,
                             hipStream_t stream);
 hipError_t art_launch_layout(const float *kappa, const float *S, int nx, int ny, int nz, int nb,
@@ -88,7 +90,7 @@ int art_max_bucket_dirs(int nside, int subsets);
 // Sets the thread-local error text returned by art_last_error; returns code.
 int art_set_error(int code, const char *msg);
 int art_march_max_lds_bytes();
-int art_march_lds_floats(int depth, int nb);
+int art_march_lds_floats(int depth, int nb, int regions = 1);
 // Shape, bins, cell size and device field records ([cell][nb] {kappa h,
 // 1/(kappa h), S, 0}; NULL before art_set_fields) of a mesh.
 void art_mesh_fields(const art_mesh *mesh, int dims[3], int *nb, double *h, const float2 **fields);

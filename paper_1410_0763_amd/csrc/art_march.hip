@@ -227,7 +227,7 @@ __device__ __forceinline__ void segment(const float *kh, const float *Sv, const 
 template <int NB, int K>
 __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restrict__ items,
                                                         const ArtMeshDesc *__restrict__ meshes,
-                                                        unsigned int *__restrict__ seg_count)
+                                                        unsigned int *__restrict__ seg_count, int priv_acc)
 {
     extern __shared__ __align__(16) float lds[];
     const int it_mesh = __builtin_amdgcn_readfirstlane(items[blockIdx.x].mesh);
@@ -295,10 +295,16 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     const bool last_a = d0 + nslab >= Na;
     const int csrc4 = (rw >= 1 ? lane - 8 : lane) << 2;   // ds_bpermute byte address
 
-    // LDS accumulators: per cell of the block, {A1, A2} of every bin.
+    // LDS accumulators: per cell of the block, {A1, A2} of every bin; with
+    // priv_acc one region per wave (no atomics; the regions are added in wave
+    // order at the flush, so the sums do not depend on timing), else one
+    // region for the workgroup.
     const int V = depth * 64;                             // cells of one block
-    float *accl = lds;
-    for (int i = threadIdx.x; i < NB * 2 * V; i += blockDim.x) accl[i] = 0.0f;
+    const int region = NB * 2 * V;
+    const bool priv = priv_acc != 0 && nwave > 1;
+    const int nreg = priv ? nwave : 1;
+    float *accl = lds + (priv ? wave * region : 0);
+    for (int i = threadIdx.x; i < nreg * region; i += blockDim.x) lds[i] = 0.0f;
     __syncthreads();
 
     // Field records of the block: base at its lowest cell, lane offset fixed,
@@ -509,8 +515,8 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             if (in_dom) {
                 const int la = (sig_neg ? Na - 1 - i : i) - lo_a;
                 float *cellacc = accl + (la * 64 + lane) * (2 * NB);
-                if (nwave == 1) {
-                    // a single wave owns the block: plain read-modify-write
+                if (nwave == 1 || priv) {
+                    // the wave owns its region: plain read-modify-write
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         cellacc[2 * b] += a1[b];
@@ -545,7 +551,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 
     // workgroup total of marched segments of positive length (work accounting)
     const unsigned int nseg = sseg * (unsigned)__popcll(__ballot(in_dom));
-    unsigned int *wg_count = reinterpret_cast<unsigned int *>(lds + NB * 2 * V);
+    unsigned int *wg_count = reinterpret_cast<unsigned int *>(lds + nreg * region);
     if (threadIdx.x == 0) *wg_count = 0u;
     __syncthreads();
     if (lane == 0) atomicAdd(wg_count, nseg);
@@ -559,6 +565,11 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
     // slabs of a column run along x, so consecutive threads take consecutive
     // slabs.  (Component-fastest or tile-row-fastest orders scatter each store
     // instruction over 8 or 64 cache lines and made the march 7-9% slower.)
+    auto accv = [&](int x) {     // a block cell's sum over the regions
+        float v = lds[x];
+        for (int w = 1; w < nreg; ++w) v += lds[w * region + x];
+        return v;
+    };
     g_f *dst = (g_f *)M.acc + (long long)it_bucket * NB * 2 * M.ncell;
     if (cls != 0 && (M.ncell & 3) == 0 && (M.nx & 3) == 0) {
         const int ng = nslab * 16;                // groups of four cells per component
@@ -573,7 +584,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int cbk = 4 * half + k;
-                v[k] = accl[(la * 64 + rwl * 8 + (bneg ? 7 - cbk : cbk)) * (2 * NB) + comp];
+                v[k] = accv((la * 64 + rwl * 8 + (bneg ? 7 - cbk : cbk)) * (2 * NB) + comp);
             }
             const long long wc = (lo_a + la) * sa + (long long)cb0 * sb + (long long)cc * sc;
             if (cb0 + 3 < Nb) {
@@ -592,7 +603,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
             if (cb >= Nb || cc >= Nc) continue;
             const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
-            dst[comp * M.ncell + wc] = accl[(la * 64 + l) * (2 * NB) + comp];
+            dst[comp * M.ncell + wc] = accv((la * 64 + l) * (2 * NB) + comp);
         }
     } else {
         for (int idx = threadIdx.x; idx < NB * 2 * V; idx += blockDim.x) {
@@ -602,7 +613,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             const int cc = lo_c + (cneg ? 7 - (l >> 3) : (l >> 3));
             if (la >= nslab || cb >= Nb || cc >= Nc) continue;
             const long long wc = (lo_a + la) * sa + cb * sb + cc * sc;
-            dst[comp * M.ncell + wc] = accl[cell * (2 * NB) + comp];
+            dst[comp * M.ncell + wc] = accv(cell * (2 * NB) + comp);
         }
     }
 }
@@ -611,13 +622,14 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 
 int art_march_max_lds_bytes() { return 160 * 1024; }
 
-// LDS floats of one workgroup: accumulators of depth * 64 cells plus a counter.
-int art_march_lds_floats(int depth, int nb) { return nb * 2 * depth * 64 + 32; }
+// LDS floats of one workgroup: accumulators of depth * 64 cells (one region,
+// or one per wave with private accumulators) plus a counter.
+int art_march_lds_floats(int depth, int nb, int regions) { return regions * nb * 2 * depth * 64 + 32; }
 
 
 template <int NB, int K>
 hipError_t launch_nbk(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, size_t bytes,
-                      int threads, unsigned int *seg_count, hipStream_t stream)
+                      int threads, unsigned int *seg_count, int priv, hipStream_t stream)
 {
     // Up to 64 KiB of local memory needs no opt-in; beyond, one opt-in to the
     // whole of it, made once (a function-local static: thread-safe).
@@ -627,33 +639,33 @@ hipError_t launch_nbk(const ArtItem *items, int nitems, const ArtMeshDesc *meshe
     if (bytes > 64 * 1024 && cfg != hipSuccess) return cfg;
     if (nitems <= 0) return hipSuccess;   // a call without items only configures the kernel
     hipLaunchKernelGGL((art_march_kernel<NB, K>), dim3(nitems), dim3(threads), bytes, stream, items,
-                       meshes, seg_count);
+                       meshes, seg_count, priv);
     return hipGetLastError();
 }
 
 template <int NB>
 hipError_t launch_nb(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int K, size_t bytes,
-                     int threads, unsigned int *seg_count, hipStream_t stream)
+                     int threads, unsigned int *seg_count, int priv, hipStream_t stream)
 {
     switch (K) {
-    case 1: return launch_nbk<NB, 1>(items, nitems, meshes, bytes, threads, seg_count, stream);
-    case 2: return launch_nbk<NB, 2>(items, nitems, meshes, bytes, threads, seg_count, stream);
-    case 4: return launch_nbk<NB, 4>(items, nitems, meshes, bytes, threads, seg_count, stream);
-    case 3: return launch_nbk<NB, 3>(items, nitems, meshes, bytes, threads, seg_count, stream);
+    case 1: return launch_nbk<NB, 1>(items, nitems, meshes, bytes, threads, seg_count, priv, stream);
+    case 2: return launch_nbk<NB, 2>(items, nitems, meshes, bytes, threads, seg_count, priv, stream);
+    case 4: return launch_nbk<NB, 4>(items, nitems, meshes, bytes, threads, seg_count, priv, stream);
+    case 3: return launch_nbk<NB, 3>(items, nitems, meshes, bytes, threads, seg_count, priv, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t art_launch_march(const ArtItem *items, int nitems, const ArtMeshDesc *meshes, int nb,
                             int interleave, int lds_floats, int threads, unsigned int *seg_count,
-                            hipStream_t stream)
+                            hipStream_t stream, int priv)
 {
     const size_t bytes = (size_t)lds_floats * sizeof(float);
     switch (nb) {
-    case 1: return launch_nb<1>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
-    case 2: return launch_nb<2>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
-    case 3: return launch_nb<3>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
-    case 4: return launch_nb<4>(items, nitems, meshes, interleave, bytes, threads, seg_count, stream);
+    case 1: return launch_nb<1>(items, nitems, meshes, interleave, bytes, threads, seg_count, priv, stream);
+    case 2: return launch_nb<2>(items, nitems, meshes, interleave, bytes, threads, seg_count, priv, stream);
+    case 3: return launch_nb<3>(items, nitems, meshes, interleave, bytes, threads, seg_count, priv, stream);
+    case 4: return launch_nb<4>(items, nitems, meshes, interleave, bytes, threads, seg_count, priv, stream);
     default: return hipErrorInvalidValue;
     }
 }
