@@ -443,7 +443,7 @@ struct art_batch {
     ArtMeshDesc *descs = nullptr; size_t descs_cap = 0;
     ArtItem *items = nullptr; size_t items_cap = 0;
     unsigned int *seg_count = nullptr; size_t seg_cap = 0;
-    struct Launch { int off, n, nb, lds, interleave, chain; };
+    struct Launch { int off, n, nb, lds, interleave, chain, waves, priv; };
     std::vector<Launch> launches;
     std::vector<int> mesh_chain;        // chain (stream of the captured graph) of each mesh
     int nchain = 1;
@@ -491,7 +491,7 @@ int batch_enqueue(art_batch *B, hipStream_t st)
     // builds them and art_batch_launch rebuilds those a plain sweep replaced)
     for (const auto &L : B->launches)
         if ((rc = chk(art_launch_march(B->items + L.off, L.n, B->descs, L.nb, L.interleave, L.lds,
-                                       64 * B->waves, B->seg_count + L.off, side[L.chain])))) return rc;
+                                       64 * L.waves, B->seg_count + L.off, side[L.chain], L.priv)))) return rc;
     for (int i = 0; i < n; ++i) {
         art_mesh *m = B->meshes[i];
         const art_outputs &o = B->outs[i];
@@ -1015,7 +1015,19 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         for (auto &kv : groups) {
             art_batch::Launch L{(int)flat.size(), (int)kv.second.size(), std::get<1>(kv.first),
                                 lds[kv.first], std::get<2>(kv.first),
-                                chains[std::make_pair(std::get<1>(kv.first), std::get<2>(kv.first))]};
+                                chains[std::make_pair(std::get<1>(kv.first), std::get<2>(kv.first))],
+                                waves, 0};
+            // small launches: several waves per workgroup with per-wave
+            // accumulators, as in the plain sweep (the regions sized for the
+            // launch's deepest mesh)
+            if (waves == 1)
+                for (int W : {4, 2})
+                    if (L.n * W <= 3072 && (long long)(W * (L.lds - 32) + 32) * 4 <= art_march_max_lds_bytes()) {
+                        L.waves = W;
+                        L.priv = 1;
+                        L.lds = W * (L.lds - 32) + 32;
+                        break;
+                    }
             flat.insert(flat.end(), kv.second.begin(), kv.second.end());
             B->launches.push_back(L);
         }
@@ -1032,7 +1044,7 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
         if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, std::string("batch setup: ") + hipGetErrorString(e)); }
         // the march kernels may need more LDS than the default: set it before capture
         for (const auto &L : B->launches) {
-            e = art_launch_march(nullptr, 0, nullptr, L.nb, L.interleave, L.lds, 64 * waves, nullptr, B->cap);
+            e = art_launch_march(nullptr, 0, nullptr, L.nb, L.interleave, L.lds, 64 * L.waves, nullptr, B->cap);
             if (e != hipSuccess) { batch_free(B); return fail(ART_E_HIP, hipGetErrorString(e)); }
         }
         e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
