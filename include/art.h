@@ -115,7 +115,13 @@ int art_set_heating(art_mesh *mesh, const float *heat_in, const float *heat_src)
  * of the last (nside, direction range, I_bc) are kept on the device and
  * reused.  Buffers grow on the first sweep at a larger Nside (this
  * synchronises the device); while a live batch holds the mesh such a sweep
- * gives ART_E_STATE instead. */
+ * gives ART_E_STATE instead.  Device memory beyond the fields and outputs:
+ * per direction the ray-state slots (NB floats per lattice ray) and the
+ * block-face buffers (NB floats x (32 depth + 64) per block of the largest
+ * cross-section, depth the tuned block depth), and per bucket one
+ * accumulator copy (2 NB floats per cell): about 3 + 3 + 13 GB at 256^3,
+ * Nside 8, 4 bins.  ART_E_UNSUPPORTED when one bucket's slots or face
+ * buffers would exceed 2 GiB. */
 int art_sweep(art_mesh *mesh, int nside, const float *gamma_w, float I_bc,
               const art_outputs *out, void *hip_stream);
 
