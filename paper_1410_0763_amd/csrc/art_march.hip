@@ -61,12 +61,12 @@
 //   A1 += ds * I * phi        (sum_j dtau_j Ibar_in,j / sum_j dtau_j per direction)
 //   A2 += ds * (1 - phi)      (exact path average of the source term)
 //   I  <- I e^{-x} + S x phi  (x phi = 1 - e^{-x}; two positive terms)
-// For x >= 1/8, phi ds = (1 - e^{-x}) |n_a| / (kappa h) with e^{-x} from
-// v_exp_f32; for x < 1/8, (1 - phi) ds = x q(x) ds with q(x) = (x - 1 +
+// e^{-x} comes from v_exp_f32.  For x >= 1/8, phi ds = (1 - e^{-x}) |n_a| /
+// (kappa h); for x < 1/8, (1 - phi) ds = x q(x) ds with q(x) = (x - 1 +
 // e^{-x}) / x^2 from a degree-2 polynomial (relative error below 1.2e-6), so
 // that neither phi nor 1 - phi cancels.  In both branches
-// x phi = (phi ds) (kappa h / |n_a|).  Slab geometry is double precision;
-// transfer is single precision.
+// S x phi = (phi ds) (S kappa h / |n_a|), the factor formed once per slab.
+// Slab geometry is double precision; transfer is single precision.
 #include "art_internal.h"
 
 namespace {
@@ -192,18 +192,16 @@ __device__ __forceinline__ void lds_add(float *p, float v)
 #define ART_YSMALL ((float)(-0.125 / ART_LN2))   // x < 1/8
 
 template <int NB>
-__device__ __forceinline__ void segment(const float *kh, const float *Sv, const float *fw,
-                                        const float *ifw, float invwl, float ds, float *I,
-                                        float *a1, float *a2)
+__device__ __forceinline__ void segment(const float *kh, const float *fw, const float *sfw,
+                                        float invwl, float ds, float *I, float *a1, float *a2)
 {
     const float dsl = ds * invwl;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const float y = kh[b] * dsl;                     // -x log2(e)
+        const float e = __builtin_amdgcn_exp2f(y);      // e^{-x}
         // large-x branch
-        const float el = __builtin_amdgcn_exp2f(y);     // e^{-x}
-        const float e1l = 1.0f - el;
-        const float lphil = e1l * fw[b];
+        const float lphil = (1.0f - e) * fw[b];
         const float lpsil = ds - lphil;
         // small-x branch (relative error below 1.2e-6 for x < 1/8)
         const float r = fmaf(y, fmaf(y, ART_R2, ART_R1), ART_R0);
@@ -212,16 +210,12 @@ __device__ __forceinline__ void segment(const float *kh, const float *Sv, const 
         const bool small = y > ART_YSMALL;
         const float lphi = small ? lphis : lphil;
         const float lpsi = small ? lpsis : lpsil;
-        // 1 - e^{-x} = x phi = (phi ds) (kappa h / |n_a|) in either branch
-        const float e1 = lphi * ifw[b];
-        // e^{-x}: from the exponential where it may be small, 1 - (1 - e^{-x})
-        // where it is above 0.88; both terms of the update are then positive
-        // (the form I + (S - I)(1 - e^{-x}) cancels when a bright ray enters
-        // an opaque cell)
-        const float e = small ? 1.0f - e1 : el;
         a1[b] = fmaf(I[b], lphi, a1[b]);
         a2[b] += lpsi;
-        I[b] = fmaf(I[b], e, Sv[b] * e1);
+        // I e^{-x} + S (1 - e^{-x}), two positive terms (the form
+        // I + (S - I)(1 - e^{-x}) cancels when a bright ray enters an opaque
+        // cell), with S (1 - e^{-x}) = (phi ds) S kappa h / |n_a|
+        I[b] = fmaf(I[b], e, lphi * sfw[b]);
     }
 }
 
@@ -443,14 +437,17 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             float rk[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) rk[b] = __builtin_amdgcn_rcpf(kh[b]);
-            // |n_a| / (kappa h), its inverse, and -log2(e) kappa h / |n_a|
-            float fw[K][NB], ifw[K][NB];
+            // |n_a| / (kappa h) and S kappa h / |n_a| per direction and bin
+            float skh[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) skh[b] = Sv[b] * kh[b];
+            float fw[K][NB], sfw[K][NB];
 #pragma unroll
             for (int m = 0; m < K; ++m)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     fw[m][b] = rk[b] * wdir[m];
-                    ifw[m][b] = kh[b] * invw[m];
+                    sfw[m][b] = skh[b] * invw[m];
                 }
             float a1[NB], a2[NB];
 #pragma unroll
@@ -486,7 +483,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
             for (int m = 0; m < K; ++m) {
                 if (!act[m]) continue;
                 sseg += codes[m] >> 5;
-                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].x), I[m], a1, a2);
+                segment<NB>(kh, fw[m], sfw[m], invwl[m], __uint_as_float(gcur[m].x), I[m], a1, a2);
             }
             // phase 2: first move of every direction, then its second segment
 #pragma unroll
@@ -498,7 +495,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m] || !(codes[m] & 3u)) continue;
-                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].y), I[m], a1, a2);
+                segment<NB>(kh, fw[m], sfw[m], invwl[m], __uint_as_float(gcur[m].y), I[m], a1, a2);
             }
             // phase 3: second move and third segment
 #pragma unroll
@@ -510,7 +507,7 @@ __global__ __launch_bounds__(512) void art_march_kernel(const ArtItem *__restric
 #pragma unroll
             for (int m = 0; m < K; ++m) {
                 if (!act[m] || !((codes[m] >> 2) & 3u)) continue;
-                segment<NB>(kh, Sv, fw[m], ifw[m], invwl[m], __uint_as_float(gcur[m].z), I[m], a1, a2);
+                segment<NB>(kh, fw[m], sfw[m], invwl[m], __uint_as_float(gcur[m].z), I[m], a1, a2);
             }
 
             if (in_dom) {

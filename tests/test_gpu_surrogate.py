@@ -528,8 +528,11 @@ def _pairs(model, mesh, idx, train, lam):
     return out
 
 
-# training recipe of the gain test (the benchmark trains the same way on more fields)
-GAIN_TRAIN_FIELDS, GAIN_STEPS, GAIN_LAMBDA = 32, 2400, 1.0
+# training recipe of the gain test (the benchmark trains the same way on 512
+# fields).  With 32 fields and 2400 steps the held-out gain moved between 4.5%
+# and 7.7% with rounding-level changes of the sweep's arithmetic; 64 fields and
+# 4800 steps, judged over 8 held-out fields, keep it well clear of the margin.
+GAIN_TRAIN_FIELDS, GAIN_STEPS, GAIN_LAMBDA, GAIN_HELD_OUT = 64, 4800, 1.0, 8
 GAIN_MARGIN = 0.05          # held-out relative L2 of J at least 5% below the coarse sweep's
 
 
@@ -557,7 +560,7 @@ def test_surrogate_gain_and_fallback():
     for p in train:
         p["X"] = torch.zeros((model.V, 16), dtype=torch.int16, device="cuda")
         model.features(p["Jc"], p["n"], p["x"], p["X"])
-    test = _pairs(model, mesh, range(4), False, GAIN_LAMBDA)
+    test = _pairs(model, mesh, range(GAIN_HELD_OUT), False, GAIN_LAMBDA)
     t0 = time.perf_counter()
     for it in range(GAIN_STEPS):
         lr = 1e-3 * 0.5 * (1 + np.cos(np.pi * it / GAIN_STEPS)) + 1e-5
