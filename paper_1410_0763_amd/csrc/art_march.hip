@@ -200,8 +200,8 @@ __device__ __forceinline__ void segment(const float *kh, const float *fw, const 
     for (int b = 0; b < NB; ++b) {
         const float y = kh[b] * dsl;                     // -x log2(e)
         const float e = __builtin_amdgcn_exp2f(y);      // e^{-x}
-        // large-x branch
-        const float lphil = (1.0f - e) * fw[b];
+        // large-x branch: (1 - e^{-x}) |n_a| / (kappa h), one rounding
+        const float lphil = fmaf(-e, fw[b], fw[b]);
         const float lpsil = ds - lphil;
         // small-x branch (relative error below 1.2e-6 for x < 1/8)
         const float r = fmaf(y, fmaf(y, ART_R2, ART_R1), ART_R0);
