@@ -757,8 +757,11 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the sweep of one mesh is measured on one MI355X; "
-              "see DESIGN.md for how directions would be sharded across GPUs.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the sweep of one mesh is measured on one MI355X. "
+              "Across GPUs each would sweep a contiguous range of the directions "
+              "(art_sweep_range, ranges balanced by segment count) and one all-reduce of the "
+              "per-cell sums would precede the normalisation; that path is not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -39,7 +39,7 @@ enum {
     ART_E_NOMEM = -2,        /* device or host allocation failed */
     ART_E_HIP = -3,          /* a HIP runtime call failed */
     ART_E_STATE = -4,        /* call out of order (e.g. sweep before set_fields) */
-    ART_E_UNSUPPORTED = -5   /* valid request this build does not handle */
+    ART_E_UNSUPPORTED = -5   /* valid request the library does not handle */
 };
 
 #define ART_MAX_BINS 4       /* frequency bins per mesh (Sect. 2.2 multi-bin form) */

@@ -22,7 +22,7 @@
  *   - OpenMP runs the rays of one ray group (Sect. 3.1) in parallel: rays of a
  *     group never share a cell, so the per-direction scratch needs no locks.
  *
- * Readings of points the paper leaves open (each one is listed in the design doc):
+ * Readings of points the paper leaves open:
  *   Q1 ray lattice: for direction n with dominant axis a (sign sig) and the
  *      other two axes b < c, ray (j,k) is the line
  *         x_a = s (sig>0) or N_a - s (sig<0),  x_b = j + 1/2 + t_b s,
