@@ -69,6 +69,10 @@ struct art_mesh {
     long long ncell = 0;
     int nb = 0;                         // bins loaded (0: no fields yet)
     art_tuning tune{6, 1, 1, 3};
+    // No shape set by the caller (art_set_tuning, an autotuner): depth 8 for
+    // one bin, else 6, and per plain sweep min(3, directions per bucket)
+    // directions per wave (march_k; a batch keeps 3).
+    bool shape_auto = true;
     float heat[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // heating weights: J_in terms, then S terms
     int mbd = 0, mbd_key[2] = {-1, -1};   // largest bucket (directions) for (nside, subsets)
 
@@ -118,6 +122,17 @@ struct art_mesh {
     // graphs, so nothing may reallocate them, re-tune the mesh or free it.
     int batches = 0;
 };
+
+namespace {
+// Directions one wave marches together in a sweep at this Nside: the tuned
+// value, or, for a mesh without a set shape, one per direction of a bucket up
+// to 3 (12 Nside^2 directions over 24 buckets: 1 at Nside 1, 2 at Nside 2).
+int march_k(const art_mesh *m, int nside)
+{
+    if (!m->shape_auto) return m->tune.interleave;
+    return nside == 1 ? 1 : (nside == 2 ? 2 : 3);
+}
+}  // namespace
 
 void art_mesh_heating(const art_mesh *m, float hw8[8])
 {
@@ -403,7 +418,7 @@ int run_sweep(art_mesh *m, int nside, int d_begin, int d_end, float I_bc, hipStr
                     lf = art_march_lds_floats(m->tune.depth, m->nb, W);
                     break;
                 }
-        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, m->tune.interleave, lf,
+        HIPCHK(art_launch_march(m->items + m->wave_off[w], n, m->desc, m->nb, march_k(m, nside), lf,
                                 64 * waves, m->seg_count + m->wave_off[w], st, priv));
     }
     HIPCHK(hipEventRecord(m->ev[2], st));
@@ -617,7 +632,9 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
         if (!m || !kappa || !S) return fail(ART_E_INVAL, "null mesh or field pointer");
         if (nbins < 1 || nbins > ART_MAX_BINS)
             return fail(ART_E_UNSUPPORTED, "nbins must be in [1, " + std::to_string(ART_MAX_BINS) + "]");
-        int rc = validate_tuning(m->tune, nbins);
+        art_tuning tn = m->tune;
+        if (m->shape_auto) tn.depth = nbins == 1 ? 8 : 6;
+        int rc = validate_tuning(tn, nbins);
         if (rc) return rc;
         if (m->batches > 0 && nbins != m->nb)
             return fail(ART_E_STATE, "mesh is held by a live batch: its bin count cannot change");
@@ -650,6 +667,10 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
             for (float &w : m->heat) w = 0.0f;   // weights belong to the old bins
         }
         m->nb = nbins;
+        if (tn.depth != m->tune.depth) {
+            m->tune = tn;
+            m->desc_valid = false;
+        }
         g_err.clear();
         return ART_OK;
     } catch (const std::bad_alloc &) {
@@ -727,11 +748,16 @@ int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_
     float *scratch = nullptr;
     size_t cap = 0;
     art_tuning saved{};
-    if (m) saved = m->tune;
+    bool saved_auto = true;
+    if (m) {
+        saved = m->tune;
+        saved_auto = m->shape_auto;
+    }
     auto done = [&](int rc) {
         if (scratch) (void)hipFree(scratch);
         if (rc != ART_OK && m) {
             m->tune = saved;
+            m->shape_auto = saved_auto;
             m->desc_valid = false;
         }
         return rc;
@@ -755,6 +781,7 @@ int art_autotune(art_mesh *m, int nside, const art_tuning *cand, int ncand, art_
         for (const art_tuning &t : list) {
             if (validate_tuning(t, m->nb) != ART_OK) continue;     // the mesh cannot run it
             m->tune = t;
+            m->shape_auto = false;
             m->desc_valid = false;
             for (int rep = 0; rep < 2; ++rep)                        // warm-up, then timed
                 if ((rc = art_sweep_range(m, nside, 0, nd, 0.0f, scratch, nullptr, hip_stream)))
@@ -814,6 +841,7 @@ int art_autotune_class(art_mesh *m, int nside, const art_tuning *cand, int ncand
             auto it = g_tune.find(key);
             if (it != g_tune.end() && validate_tuning(it->second.t, m->nb) == ART_OK) {
                 m->tune = it->second.t;
+                m->shape_auto = false;
                 m->desc_valid = false;
                 if (best) *best = it->second.t;
                 if (best_ms) *best_ms = it->second.ms;
@@ -904,6 +932,7 @@ int art_set_tuning(art_mesh *m, const art_tuning *t)
     if (rc) return rc;
     if (m->batches > 0) return fail(ART_E_STATE, "mesh is held by a live batch: it cannot be re-tuned");
     m->tune = *t;
+    m->shape_auto = false;
     m->desc_valid = false;
     g_err.clear();
     return ART_OK;
@@ -994,14 +1023,20 @@ int art_batch_create(art_mesh *const *meshes, const int *nside, int n, const flo
             for (int q = 0; q < 8; ++q) h[q] = m->heat[q];
             B->hw.push_back(h);
             const int lf = art_march_lds_floats(m->tune.depth, m->nb);
-            const auto ck = std::make_pair(m->nb, m->tune.interleave);
+            // the tuned directions per wave; a mesh without a set shape keeps
+            // 3 here at every Nside, since each (bins, directions per wave)
+            // pair is a chain of its own and more chains than hardware queues
+            // run slower (48 uneven meshes: 81.4 ms with 2 at Nside 2, 76.5
+            // ms with 3)
+            const int mk = m->tune.interleave;
+            const auto ck = std::make_pair(m->nb, mk);
             if (!chains.count(ck)) {
                 const int c = (int)chains.size();
                 chains[ck] = c;
             }
             B->mesh_chain.push_back(chains[ck]);
             for (size_t w = 0; w + 1 < m->wave_off.size(); ++w) {
-                auto key = std::make_tuple((int)w, m->nb, m->tune.interleave);
+                auto key = std::make_tuple((int)w, m->nb, mk);
                 auto &v = groups[key];
                 for (int q = m->wave_off[w]; q < m->wave_off[w + 1]; ++q) {
                     ArtItem it = m->items_host[q];

@@ -80,3 +80,44 @@ def test_autotune_class_cache_shared_by_a_shape_class(tmp_path):
         r = mesh.autotune_class(m.nside, candidates=cands)
         assert r["cached"] and r["tuning"] == res[0]["tuning"]
     art.tune_cache("clear")
+
+
+
+def test_automatic_shape_of_an_untuned_mesh():
+    """A mesh whose shape was never set takes depth 8 for one bin and 6 for
+    more, and per sweep 1, 2 or 3 directions per wave at Nside 1, 2 and 4:
+    its sweeps are bitwise those of the same shapes set explicitly, and match
+    the oracle; after art_set_tuning the set shape holds whatever the bins."""
+    print("\n== case automatic shape: 21x18x20, 1 and 3 bins, nside 1, 2, 4", flush=True)
+    import torch
+    from paper_1410_0763_amd import art
+    m1 = media.clumpy_medium((20, 18, 21), nside=2, sigma_ln=1.0, seed=71, nbins=1, name="auto1")
+    m3 = media.clumpy_medium((20, 18, 21), nside=2, sigma_ln=1.0, seed=72, nbins=3, name="auto3")
+    nb, nz, ny, nx = m1.kappa.shape
+    dev = lambda m: (torch.from_numpy(m.kappa).cuda(), torch.from_numpy(m.S).cuda())
+    with art.Mesh(nx, ny, nz) as auto, art.Mesh(nx, ny, nz) as fixed:
+        auto.set_fields(*dev(m3))
+        assert auto.get_tuning() == dict(depth=6, subsets=1, waves=1, interleave=3)
+        auto.set_fields(*dev(m1))
+        fixed.set_fields(*dev(m1))
+        assert auto.get_tuning() == dict(depth=8, subsets=1, waves=1, interleave=3)
+        for nside, k in ((1, 1), (2, 2), (4, 3)):
+            fixed.set_tuning(8, 1, 1, k)
+            a = auto.sweep(nside, gamma_w=m1.gamma_w)
+            f = fixed.sweep(nside, gamma_w=m1.gamma_w)
+            torch.cuda.synchronize()
+            for key in ("J_in", "J", "J_exact", "Gamma"):
+                assert torch.equal(a[key], f[key]), (nside, key)
+        auto.set_heating(m1.heat_in, m1.heat_src)
+        g = {key: v.cpu().numpy() for key, v in auto.sweep(m1.nside, gamma_w=m1.gamma_w).items()}
+        compare_all(m1, g, oracle_sweep(m1))
+        # a set shape holds: the same results as the other mesh at that shape,
+        # and loading bins no longer changes it
+        auto.set_tuning(6, 1, 1, 3)
+        fixed.set_tuning(6, 1, 1, 3)
+        a = auto.sweep(2, gamma_w=m1.gamma_w)
+        f = fixed.sweep(2, gamma_w=m1.gamma_w)
+        torch.cuda.synchronize()
+        assert torch.equal(a["J"], f["J"])
+        auto.set_fields(*dev(m1))
+        assert auto.get_tuning() == dict(depth=6, subsets=1, waves=1, interleave=3)
