@@ -67,14 +67,14 @@ typedef struct {
  * along a; one workgroup of `waves` 64-lane waves marches one block for one
  * bucket of directions (one of `subsets` parts of a dominant-axis x octant
  * group).  Until a shape is set (art_set_tuning, art_autotune,
- * art_autotune_class) the mesh chooses its own: depth 8 for one bin and 6 for
- * more (set when art_set_fields loads the bins), one subset and one wave, and
+ * art_autotune_class) the mesh chooses its own: depth 8 for 1-3 bins and 6 for
+ * 4 (set when art_set_fields loads the bins), one subset and one wave, and
  * per sweep min(3, directions per bucket) directions per wave, i.e. 1 at
  * Nside 1, 2 at Nside 2 and 3 above (the 24 buckets share 12 Nside^2
  * directions).  Depth 6 with 3 directions per wave is the fastest shape
- * measured for a 256^3 mesh with 768 directions and 4 bins; for 128^3 and one
- * bin depth 8 is 7% faster at Nside 16, and with 2 directions per wave 12%
- * faster at Nside 2.  art_get_tuning then reports interleave 3, and a batch
+ * measured for a 256^3 mesh with 768 directions and 4 bins; with 1-3 bins
+ * depth 8 is 2-7% faster (128^3 and 256^3, Nside 8 and 16), and at Nside 2
+ * 2 directions per wave are 9% faster than 3.  art_get_tuning then reports interleave 3, and a batch
  * (art_sweep_batched, art_batch_create) marches such a mesh with 3 directions
  * per wave at every Nside. */
 typedef struct {

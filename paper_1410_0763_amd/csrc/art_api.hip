@@ -70,7 +70,7 @@ struct art_mesh {
     int nb = 0;                         // bins loaded (0: no fields yet)
     art_tuning tune{6, 1, 1, 3};
     // No shape set by the caller (art_set_tuning, an autotuner): depth 8 for
-    // one bin, else 6, and per plain sweep min(3, directions per bucket)
+    // 1-3 bins, 6 for 4, and per plain sweep min(3, directions per bucket)
     // directions per wave (march_k; a batch keeps 3).
     bool shape_auto = true;
     float heat[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // heating weights: J_in terms, then S terms
@@ -633,7 +633,7 @@ int art_set_fields(art_mesh *m, int nbins, const float *kappa, const float *S, i
         if (nbins < 1 || nbins > ART_MAX_BINS)
             return fail(ART_E_UNSUPPORTED, "nbins must be in [1, " + std::to_string(ART_MAX_BINS) + "]");
         art_tuning tn = m->tune;
-        if (m->shape_auto) tn.depth = nbins == 1 ? 8 : 6;
+        if (m->shape_auto) tn.depth = nbins <= 3 ? 8 : 6;   // 4 bins at depth 8: 2 workgroups per SIMD
         int rc = validate_tuning(tn, nbins);
         if (rc) return rc;
         if (m->batches > 0 && nbins != m->nb)
