@@ -49,7 +49,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // One step of the cell walk: the segment from t to the nearest plane
 // crossing (its cell and its length), then the move to the next cell across
-// that plane (ties: x, y, z).
+// that plane (ties: x, y, z).  The next crossing of the axis crossed is
+// t_n + 1 * dt and of the others t_n + 0 * dt, one multiply-add each with
+// the same value as the sum or t_n itself (dt is finite: a direction
+// without a component along an axis has t_n = inf and dt = 1e300 there).
 __device__ __forceinline__ void walk_step(double &tnx, double &tny, double &tnz, double &t, int &cell,
                                           int dcx, int dcy, int dcz, double dtx, double dty,
                                           double dtz, int &cl, double &dl)
@@ -61,9 +64,9 @@ __device__ __forceinline__ void walk_step(double &tnx, double &tny, double &tnz,
     const bool mx = tnx == tmin;
     const bool my = !mx && tny == tmin;
     cell += mx ? dcx : (my ? dcy : dcz);
-    tnx += mx ? dtx : 0.0;
-    tny += my ? dty : 0.0;
-    tnz += (!mx && !my) ? dtz : 0.0;
+    tnx = fma(mx ? 1.0 : 0.0, dtx, tnx);
+    tny = fma(my ? 1.0 : 0.0, dty, tny);
+    tnz = fma((!mx && !my) ? 1.0 : 0.0, dtz, tnz);
 }
 
 // kappa h of the NB bins of one cell from the pack (KS floats per cell);
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(256) void art_point_kernel(const float *__restrict_
         double tnx = ux > 0.0 ? (ix + 1.0 - px) * ix_ : (ux < 0.0 ? (ix - px) * ix_ : INFINITY);
         double tny = uy > 0.0 ? (iy + 1.0 - py) * iy_ : (uy < 0.0 ? (iy - py) * iy_ : INFINITY);
         double tnz = uz > 0.0 ? (iz + 1.0 - pz) * iz_ : (uz < 0.0 ? (iz - pz) * iz_ : INFINITY);
-        const double dtx = fabs(ix_), dty = fabs(iy_), dtz = fabs(iz_);
+        const double dtx = fmin(fabs(ix_), 1e300), dty = fmin(fabs(iy_), 1e300), dtz = fmin(fabs(iz_), 1e300);
         double tau[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) tau[b] = 0.0;
